@@ -1,0 +1,192 @@
+/*
+ * axf.h -- C ABI of the MI355X (gfx950) axisymmetric modal FMM library.
+ *
+ * The library evaluates, for azimuthal modes n = 0..N, the modal potential
+ *
+ *     Phi^(n)(r_j, z_j) = sum_i S_i^(n) G^(n)(r_j, r_i, z_j - z_i)
+ *
+ * of ring sources at (r_i, z_i) with complex Fourier strengths S_i^(n), at
+ * field points (r_j, z_j), where G^(n)(r, r1, x) = Q_{n-1/2}(chi) /
+ * (2 pi sqrt(r r1)), chi = (r^2 + r1^2 + x^2) / (2 r r1), is the modal Green's
+ * function of Carley, "A Fast Multipole Method for axisymmetric domains"
+ * (arXiv 2301.01179), eqs. analysis:gfunc and analysis:sum.  The sum is
+ * approximated by the paper's uniform (r, z) quadtree FMM (Algorithm 1):
+ * Taylor tables of G built by the Laplace-equation derivative recursion
+ * (App. A), moments (eq. analysis:moments), moment shift (eq. analysis:shift),
+ * source-to-local operators with the FO/BO/FI/BI reuse (section 2.2,
+ * eq. analysis:s2l), local shift (eq. analysis:l2l) and direct near-field
+ * sums over the 3x3 neighbour leaves.
+ *
+ * Conventions (all entry points):
+ *   - Every array argument is a DEVICE pointer unless marked "host".
+ *   - Complex numbers are interleaved (re, im) doubles (complex128).
+ *   - Strengths S: complex128 [nrhs][n_modes][ns]; potentials phi: complex128
+ *     [nrhs][n_modes][nf]; both in the caller's point order.
+ *   - The caller owns every buffer it passes; the library keeps no reference
+ *     to them after the enqueued work completes.  Buffers must stay alive
+ *     until the work on `stream` has finished (ordinary stream semantics).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   - A source whose (r, z) equals a field point bit for bit does not act on
+ *     it (no self interaction; the log singularity is excluded).
+ *   - Errors are returned as status codes and never thrown; axf_last_error()
+ *     returns a thread-local description of the last failure.  An argument
+ *     error enqueues no work.  Asynchronous kernel failures surface as
+ *     AXF_ERR_HIP on a later call.
+ *   - A plan must not be used on two streams at the same time.
+ */
+#ifndef AXF_H
+#define AXF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AXF_OK = 0,
+    AXF_ERR_INVALID_ARGUMENT = 1,  /* null pointer, negative size, bad params  */
+    AXF_ERR_INVALID_GEOMETRY = 2,  /* r <= 0, or a non-finite coordinate       */
+    AXF_ERR_OUT_OF_MEMORY = 3,     /* device allocation failed                 */
+    AXF_ERR_UNSUPPORTED = 4,       /* order, modes or depth beyond the limits  */
+    AXF_ERR_HIP = 5                /* a HIP runtime call failed                */
+} axf_status;
+
+/* Limits of this build. */
+#define AXF_MAX_MODES 64   /* n_modes = N + 1 <= 64                     */
+#define AXF_MAX_ORDER 24   /* expansion order M <= 24                   */
+#define AXF_MAX_DEPTH 11   /* tree depth d <= 11                        */
+#define AXF_MAX_RHS 8      /* right-hand sides per plan                 */
+
+/* Plan parameters.
+ *   n_modes : N + 1, modes n = 0..N (1 <= n_modes <= AXF_MAX_MODES).
+ *   order   : expansion order M of moments and locals; moments S_ij with
+ *             i + j <= M, locals Phi_kl with k + l <= M, derivative tables to
+ *             total order 2M (0 <= M <= AXF_MAX_ORDER).
+ *   depth   : tree depth d (2 <= d <= AXF_MAX_DEPTH), or 0 to choose the
+ *             smallest d >= 2 with at most max_leaf sources and at most
+ *             max_leaf field points in every leaf (capped at AXF_MAX_DEPTH).
+ *   max_leaf: leaf bound used when depth == 0 (>= 1).
+ *   nrhs    : right-hand sides sharing the geometry (1..AXF_MAX_RHS).
+ *   flags   : reserved, pass 0. */
+typedef struct {
+    int32_t n_modes;
+    int32_t order;
+    int32_t depth;
+    int32_t max_leaf;
+    int32_t nrhs;
+    uint32_t flags;
+} axf_params;
+
+typedef struct axf_plan axf_plan;   /* opaque; owned by the library */
+
+/* Build a plan for fixed source and field points (Algorithm 1, first two
+ * steps, plus the Taylor tables of App. A for every level, radial station
+ * and the twelve separations of section 2.2).
+ *   r_src, z_src : [ns] source ring radii and axial stations (device).
+ *   r_fld, z_fld : [nf] field points (device).  May alias the sources.
+ * The plan copies what it needs; the coordinate buffers may be freed after
+ * the call returns.  This call synchronises `stream` (it reads back the
+ * bounding square and the tree occupancy) and allocates device memory.
+ * Returns AXF_ERR_INVALID_GEOMETRY if any r <= 0 or any coordinate is not
+ * finite; ns >= 1 and nf >= 1 are required. */
+axf_status axf_plan_create(const axf_params *params,
+                           int64_t ns, const double *r_src, const double *z_src,
+                           int64_t nf, const double *r_fld, const double *z_fld,
+                           void *stream, axf_plan **out_plan);
+
+/* Release the plan and its device memory (after pending work on the plan's
+ * last stream has finished).  NULL is accepted. */
+void axf_plan_destroy(axf_plan *plan);
+
+/* FMM evaluation (Algorithm 1: moments, upward pass, downward pass, leaf
+ * evaluation).  S: complex128 [nrhs][n_modes][ns]; phi: complex128
+ * [nrhs][n_modes][nf], overwritten.  Asynchronous on `stream`; allocates
+ * nothing. */
+axf_status axf_evaluate(axf_plan *plan, const double *S, double *phi, void *stream);
+
+/* FMM evaluation that also returns the field gradient at the field points:
+ * dphi_dr = dPhi/dr, dphi_dz = dPhi/dz, same layout as phi (each may be
+ * NULL).  The far field is differentiated through the local expansion, the
+ * near field through the first-derivative starting formulas of App. A. */
+axf_status axf_evaluate_grad(axf_plan *plan, const double *S, double *phi,
+                             double *dphi_dr, double *dphi_dz, void *stream);
+
+/* Direct O(ns * nf) modal sum (eq. analysis:sum) on the GPU, same
+ * arguments and layout as axf_evaluate.  Uses only the plan's points. */
+axf_status axf_evaluate_direct(axf_plan *plan, const double *S, double *phi, void *stream);
+
+/* Adjoint of axf_evaluate for a real loss L(Phi).
+ *   gphi : complex128 [nrhs][n_modes][nf], dL/dRe(Phi) + i dL/dIm(Phi).
+ *   gS   : complex128 [nrhs][n_modes][ns], overwritten with dL/dRe(S) +
+ *          i dL/dIm(S) (the transposed FMM: G is real and symmetric, so this
+ *          is the FMM with the roles of sources and field points swapped).
+ *   S, g_rsrc, g_zsrc : if g_rsrc or g_zsrc is non-NULL, S must be given and
+ *          g_rsrc[ns] = dL/dr_i, g_zsrc[ns] = dL/dz_i of the source rings are
+ *          overwritten (summed over modes and right-hand sides).
+ * The plan's sources and field points share one tree, so gS is the exact
+ * transpose of axf_evaluate up to rounding. */
+axf_status axf_adjoint(axf_plan *plan, const double *S, const double *gphi,
+                       double *gS, double *g_rsrc, double *g_zsrc, void *stream);
+
+/* Plan introspection (host outputs; any pointer may be NULL). */
+axf_status axf_plan_info(const axf_plan *plan, int32_t *depth, int32_t *n_modes,
+                         int32_t *order, int32_t *nrhs, int64_t *ns, int64_t *nf,
+                         double *square4 /* host [4]: r_lo, z_lo, L, 1/L */,
+                         int64_t *n_near_pairs, int64_t *n_s2l_pairs,
+                         size_t *device_bytes);
+
+/* Number of occupied source / field boxes at `level` (host outputs). */
+axf_status axf_plan_level_info(const axf_plan *plan, int32_t level,
+                               int32_t *n_src_boxes, int32_t *n_fld_boxes);
+
+/* ---------------------------------------------------------------------- */
+/* Batched launches: many independent problems (uneven sizes, own points,
+ * own right-hand-side counts; common n_modes and order) evaluated by one
+ * launch sequence of persistent kernels that pull work items from queues
+ * built at creation, captured once in a HIP graph and replayed by
+ * axf_batch_launch. */
+typedef struct {
+    int64_t ns, nf;
+    const double *r_src, *z_src;   /* device [ns] */
+    const double *r_fld, *z_fld;   /* device [nf] */
+    const double *S;               /* device complex128 [nrhs][n_modes][ns] */
+    double *phi;                   /* device complex128 [nrhs][n_modes][nf] */
+    int32_t nrhs;                  /* 1..AXF_MAX_RHS */
+    int32_t depth;                 /* 0 = chosen by the autotuner */
+} axf_problem;
+
+typedef struct axf_batch axf_batch;
+
+/* Build the batch: per-problem trees and tables, merged work queues, and
+ * the captured graph.  params->nrhs and params->depth are ignored (taken per
+ * problem); params->max_leaf is used where a problem's depth is 0 and the
+ * autotuner is disabled (flags bit AXF_BATCH_NO_AUTOTUNE).  The problem
+ * array is host memory and is copied; the S and phi buffers it names must
+ * stay valid for every launch.  Synchronises `stream`. */
+#define AXF_BATCH_NO_AUTOTUNE 1u
+axf_status axf_batch_create(const axf_params *params, int32_t nprob,
+                            const axf_problem *problems, void *stream,
+                            axf_batch **out_batch);
+
+/* Evaluate every problem of the batch (replay of the captured graph). */
+axf_status axf_batch_launch(axf_batch *batch, void *stream);
+
+/* Evaluate every problem with per-problem plain launches (no graph, no
+ * merged queues); the reference the batched path is measured against. */
+axf_status axf_batch_launch_plain(axf_batch *batch, void *stream);
+
+/* Depth the batch chose for problem `i` (host output). */
+axf_status axf_batch_problem_depth(const axf_batch *batch, int32_t i, int32_t *depth);
+
+void axf_batch_destroy(axf_batch *batch);
+
+/* ---------------------------------------------------------------------- */
+const char *axf_status_string(axf_status status);
+const char *axf_last_error(void);   /* thread-local detail of the last error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AXF_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of libaxf.so (the gfx950 modal FMM library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory and the stream.  Tensors:
+coordinates float64 [n] on the GPU, strengths and potentials complex128
+[nrhs, n_modes, n] on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaxf.so")
+
+AXF_OK = 0
+_STATUS = {0: "AXF_OK", 1: "AXF_ERR_INVALID_ARGUMENT", 2: "AXF_ERR_INVALID_GEOMETRY",
+           3: "AXF_ERR_OUT_OF_MEMORY", 4: "AXF_ERR_UNSUPPORTED", 5: "AXF_ERR_HIP"}
+
+EXPORTED = [
+    "axf_plan_create", "axf_plan_destroy", "axf_evaluate", "axf_evaluate_grad",
+    "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
+    "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
+    "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
+]
+
+
+class AxfError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int32), ("order", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("max_leaf", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("ns", ctypes.c_int64), ("nf", ctypes.c_int64),
+                ("r_src", ctypes.c_void_p), ("z_src", ctypes.c_void_p),
+                ("r_fld", ctypes.c_void_p), ("z_fld", ctypes.c_void_p),
+                ("S", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int32), ("depth", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libaxf.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2301_01179_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    lib.axf_plan_create.argtypes = [P(Params), i64, vp, vp, i64, vp, vp, vp, P(vp)]
+    lib.axf_plan_destroy.argtypes = [vp]
+    lib.axf_plan_destroy.restype = None
+    lib.axf_evaluate.argtypes = [vp, vp, vp, vp]
+    lib.axf_evaluate_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.axf_evaluate_direct.argtypes = [vp, vp, vp, vp]
+    lib.axf_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.axf_plan_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i64),
+                                  P(ctypes.c_double), P(i64), P(i64), P(ctypes.c_size_t)]
+    lib.axf_plan_level_info.argtypes = [vp, i32, P(i32), P(i32)]
+    lib.axf_batch_create.argtypes = [P(Params), i32, P(Problem), vp, P(vp)]
+    lib.axf_batch_launch.argtypes = [vp, vp]
+    lib.axf_batch_launch_plain.argtypes = [vp, vp]
+    lib.axf_batch_problem_depth.argtypes = [vp, i32, P(i32)]
+    lib.axf_batch_destroy.argtypes = [vp]
+    lib.axf_batch_destroy.restype = None
+    lib.axf_status_string.argtypes = [ctypes.c_int]
+    lib.axf_status_string.restype = ctypes.c_char_p
+    lib.axf_last_error.argtypes = []
+    lib.axf_last_error.restype = ctypes.c_char_p
+    for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
+                 "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
+                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != AXF_OK:
+        raise AxfError(status, where, _lib.axf_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _coords(x, dev):
+    t = torch.as_tensor(x, dtype=torch.float64, device=dev)
+    return t.contiguous()
+
+
+class Plan:
+    """Tree, tables and work lists for fixed source and field points.
+
+    r_src, z_src, r_fld, z_fld: float64 tensors (or arrays) of ring radii and
+    axial stations.  n_modes = N + 1, order = M, depth 0 = automatic with at
+    most max_leaf points per leaf.
+    """
+
+    def __init__(self, r_src, z_src, r_fld, z_fld, n_modes: int, order: int, depth: int = 0,
+                 max_leaf: int = 64, nrhs: int = 1, device=None):
+        lib = load_library()
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        rs, zs = _coords(r_src, dev), _coords(z_src, dev)
+        rf, zf = _coords(r_fld, dev), _coords(z_fld, dev)
+        self.ns, self.nf = rs.numel(), rf.numel()
+        self.n_modes, self.order, self.nrhs = n_modes, order, nrhs
+        p = Params(n_modes, order, depth, max_leaf, nrhs, 0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = lib.axf_plan_create(ctypes.byref(p), self.ns, _ptr(rs), _ptr(zs), self.nf, _ptr(rf),
+                                     _ptr(zf), _stream(), ctypes.byref(h))
+        _check(st, "axf_plan_create")
+        self._h = h
+        self._coords = (rs, zs, rf, zf)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.axf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ info
+    def info(self) -> dict:
+        i32 = ctypes.c_int32
+        d, nm, m, nr = i32(), i32(), i32(), i32()
+        ns, nf, near, s2l = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        sq = (ctypes.c_double * 4)()
+        nbytes = ctypes.c_size_t()
+        _check(_lib.axf_plan_info(self._h, ctypes.byref(d), ctypes.byref(nm), ctypes.byref(m),
+                                  ctypes.byref(nr), ctypes.byref(ns), ctypes.byref(nf), sq,
+                                  ctypes.byref(near), ctypes.byref(s2l), ctypes.byref(nbytes)),
+               "axf_plan_info")
+        levels = {}
+        for lev in range(2, d.value + 1):
+            a, b = i32(), i32()
+            _check(_lib.axf_plan_level_info(self._h, lev, ctypes.byref(a), ctypes.byref(b)),
+                   "axf_plan_level_info")
+            levels[lev] = (a.value, b.value)
+        return {"depth": d.value, "n_modes": nm.value, "order": m.value, "nrhs": nr.value,
+                "ns": ns.value, "nf": nf.value, "square": tuple(sq), "near_pairs": near.value,
+                "s2l_pairs": s2l.value, "device_bytes": nbytes.value, "levels": levels}
+
+    # ------------------------------------------------------- evaluation
+    def _strengths(self, S, n):
+        S = torch.as_tensor(S, device=self.device)
+        if S.dtype != torch.complex128:
+            S = S.to(torch.complex128)
+        S = S.reshape(self.nrhs, self.n_modes, n).contiguous()
+        return S
+
+    def _out(self, n):
+        return torch.empty((self.nrhs, self.n_modes, n), dtype=torch.complex128, device=self.device)
+
+    def evaluate(self, S, out=None):
+        S = self._strengths(S, self.ns)
+        phi = self._out(self.nf) if out is None else out
+        _check(_lib.axf_evaluate(self._h, _ptr(S), _ptr(phi), _stream()), "axf_evaluate")
+        return phi
+
+    def evaluate_grad(self, S):
+        S = self._strengths(S, self.ns)
+        phi, dr, dz = self._out(self.nf), self._out(self.nf), self._out(self.nf)
+        _check(_lib.axf_evaluate_grad(self._h, _ptr(S), _ptr(phi), _ptr(dr), _ptr(dz), _stream()),
+               "axf_evaluate_grad")
+        return phi, dr, dz
+
+    def evaluate_direct(self, S, out=None):
+        S = self._strengths(S, self.ns)
+        phi = self._out(self.nf) if out is None else out
+        _check(_lib.axf_evaluate_direct(self._h, _ptr(S), _ptr(phi), _stream()), "axf_evaluate_direct")
+        return phi
+
+    def adjoint(self, gphi, S=None, coords: bool = True):
+        """(gS, g_rsrc, g_zsrc) for gphi = dL/dRe(phi) + i dL/dIm(phi)."""
+        gphi = self._strengths(gphi, self.nf)
+        gS = self._out(self.ns)
+        gr = gz = None
+        Sp = None
+        if coords:
+            if S is None:
+                raise ValueError("S is required for coordinate gradients")
+            Sp = self._strengths(S, self.ns)
+            gr = torch.empty(self.ns, dtype=torch.float64, device=self.device)
+            gz = torch.empty(self.ns, dtype=torch.float64, device=self.device)
+        _check(_lib.axf_adjoint(self._h, _ptr(Sp), _ptr(gphi), _ptr(gS), _ptr(gr), _ptr(gz), _stream()),
+               "axf_adjoint")
+        return gS, gr, gz
+
+
+class AxFMM(torch.autograd.Function):
+    """phi = FMM(S; r_src, z_src) on a fixed plan, differentiable in S and in
+    the source coordinates (through the adjoint FMM).  The coordinate
+    gradient is that of the modal sum at the current points; the plan's tree
+    is not rebuilt."""
+
+    @staticmethod
+    def forward(ctx, S, r_src, z_src, plan: Plan):
+        ctx.plan = plan
+        ctx.save_for_backward(S)
+        return plan.evaluate(S.detach())
+
+    @staticmethod
+    def backward(ctx, gphi):
+        (S,) = ctx.saved_tensors
+        plan = ctx.plan
+        need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        gS, gr, gz = plan.adjoint(gphi.contiguous(), S.detach(), coords=need_c)
+        return (gS if ctx.needs_input_grad[0] else None,
+                gr if ctx.needs_input_grad[1] else None,
+                gz if ctx.needs_input_grad[2] else None, None)
+
+
+def fmm(S, r_src, z_src, plan: Plan):
+    return AxFMM.apply(S, r_src, z_src, plan)

@@ -1,0 +1,317 @@
+// axf_api.hip -- C ABI: plan lifecycle, evaluation entry points, errors and
+// the device arena cache.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "axf_device.hpp"
+#include "axf_internal.hpp"
+
+namespace axf {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const char *get_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------- arena cache
+namespace {
+std::mutex g_cache_mu;
+std::vector<Arena> g_cache;
+size_t g_cached_bytes = 0;
+constexpr size_t kCacheLimit = size_t(32) << 30;
+}  // namespace
+
+Arena arena_acquire(size_t bytes)
+{
+    int dev = 0;
+    AXF_HIP(hipGetDevice(&dev));
+    bytes = std::max<size_t>(bytes, 256);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const Arena &a = g_cache[i];
+            if (a.device != dev || a.bytes < bytes || a.bytes > 2 * bytes + (size_t(64) << 20)) continue;
+            if (best < 0 || a.bytes < g_cache[best].bytes) best = i;
+        }
+        if (best >= 0) {
+            Arena a = g_cache[best];
+            g_cache.erase(g_cache.begin() + best);
+            g_cached_bytes -= a.bytes;
+            a.used = 0;
+            return a;
+        }
+    }
+    Arena a;
+    a.device = dev;
+    a.bytes = bytes;
+    hipError_t e = hipMalloc((void **)&a.base, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // drop the cache and retry once
+        std::vector<Arena> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            drop.swap(g_cache);
+            g_cached_bytes = 0;
+        }
+        for (Arena &x : drop) (void)hipFree(x.base);
+        e = hipMalloc((void **)&a.base, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            throw Fail{AXF_ERR_OUT_OF_MEMORY};
+        }
+    }
+    return a;
+}
+
+void arena_release(Arena &a)
+{
+    if (!a.base) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cached_bytes + a.bytes <= kCacheLimit) {
+        g_cache.push_back(a);
+        g_cached_bytes += a.bytes;
+    } else {
+        (void)hipFree(a.base);
+    }
+    a = Arena();
+}
+
+static void plan_free(Plan *pl)
+{
+    if (!pl) return;
+    (void)hipDeviceSynchronize();
+    arena_release(pl->points);
+    arena_release(pl->tree);
+    arena_release(pl->expn);
+    delete pl;
+}
+
+static void validate_params(const axf_params *p)
+{
+    AXF_REQUIRE(p != nullptr, AXF_ERR_INVALID_ARGUMENT, "params is NULL");
+    AXF_REQUIRE(p->n_modes >= 1 && p->n_modes <= AXF_MAX_MODES, AXF_ERR_UNSUPPORTED,
+                "n_modes must be in 1..64");
+    AXF_REQUIRE(p->order >= 0 && p->order <= AXF_MAX_ORDER, AXF_ERR_UNSUPPORTED, "order must be in 0..24");
+    AXF_REQUIRE(p->depth == 0 || (p->depth >= 2 && p->depth <= AXF_MAX_DEPTH), AXF_ERR_UNSUPPORTED,
+                "depth must be 0 (automatic) or in 2..11");
+    AXF_REQUIRE(p->depth != 0 || p->max_leaf >= 1, AXF_ERR_INVALID_ARGUMENT,
+                "max_leaf must be >= 1 when depth is 0");
+    AXF_REQUIRE(p->nrhs >= 1 && p->nrhs <= AXF_MAX_RHS, AXF_ERR_UNSUPPORTED, "nrhs must be in 1..8");
+}
+
+// Build everything after the parameters are known valid.
+void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, const double *zs, int64_t nf,
+                const double *rf, const double *zf, hipStream_t st)
+{
+    AXF_HIP(hipGetDevice(&pl.device));
+    pl.p = p;
+    pl.nmodes = p.n_modes;
+    pl.N = p.n_modes - 1;
+    pl.M = p.order;
+    pl.P = (p.order + 1) * (p.order + 2) / 2;
+    pl.nrhs = p.nrhs;
+    pl.C = p.n_modes * p.nrhs;
+    pl.TS = (p.order + 1) * (p.order + 1) * (p.order + 1);
+    pl.chistar = forward_chi_limit(p.n_modes);
+    pl.src.n = ns;
+    pl.fld.n = nf;
+    build_tree(pl, rs, zs, rf, zf, st);
+
+    // expansion arena: moments, locals, tables, table scratch
+    const int d = pl.d;
+    Sizer sz;
+    for (int l = 2; l <= d; ++l) {
+        size_t nb = (size_t)std::max(pl.src.nocc[l], pl.fld.nocc[l]);
+        sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
+        sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
+    }
+    size_t ngeom = 12 * (((size_t)1 << (d + 1)) - 4);
+    sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS);
+    sz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+    pl.expn = arena_acquire(sz.bytes + 4096);
+    for (int l = 2; l <= d; ++l) {
+        size_t nb = (size_t)std::max(pl.src.nocc[l], pl.fld.nocc[l]);
+        pl.lev[l].nb = 1 << l;
+        pl.lev[l].h = pl.L / (1 << l);
+        pl.lev[l].mom = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
+        pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
+    }
+    double *tab = pl.expn.take<double>(ngeom * (size_t)pl.nmodes * pl.TS);
+    for (int l = 2; l <= d; ++l)
+        pl.lev[l].tab = tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
+    pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+    build_tables(pl, st);
+    pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes;
+}
+
+}  // namespace axf
+
+using namespace axf;
+
+struct axf_plan {
+    Plan pl;
+};
+
+#define AXF_TRY(body)                                       \
+    try {                                                   \
+        body;                                               \
+        return AXF_OK;                                      \
+    } catch (const Fail &f) {                               \
+        return f.st;                                        \
+    } catch (const std::bad_alloc &) {                      \
+        set_error("host allocation failed");                \
+        return AXF_ERR_OUT_OF_MEMORY;                       \
+    } catch (...) {                                         \
+        set_error("unexpected internal error");             \
+        return AXF_ERR_HIP;                                 \
+    }
+
+extern "C" {
+
+axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r_src, const double *z_src,
+                           int64_t nf, const double *r_fld, const double *z_fld, void *stream,
+                           axf_plan **out_plan)
+{
+    axf_plan *h = nullptr;
+    try {
+        AXF_REQUIRE(out_plan != nullptr, AXF_ERR_INVALID_ARGUMENT, "out_plan is NULL");
+        *out_plan = nullptr;
+        validate_params(params);
+        AXF_REQUIRE(ns >= 1 && nf >= 1, AXF_ERR_INVALID_ARGUMENT, "ns and nf must be >= 1");
+        AXF_REQUIRE(ns < (int64_t(1) << 31) && nf < (int64_t(1) << 31), AXF_ERR_UNSUPPORTED,
+                    "ns and nf must be < 2^31");
+        AXF_REQUIRE(r_src && z_src && r_fld && z_fld, AXF_ERR_INVALID_ARGUMENT, "a coordinate pointer is NULL");
+        h = new axf_plan();
+        plan_build(h->pl, *params, ns, r_src, z_src, nf, r_fld, z_fld, (hipStream_t)stream);
+        *out_plan = h;
+        return AXF_OK;
+    } catch (const Fail &f) {
+        if (h) plan_free(&h->pl), h = nullptr;
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return AXF_ERR_OUT_OF_MEMORY;
+    }
+}
+
+void axf_plan_destroy(axf_plan *plan)
+{
+    if (!plan) return;
+    Plan *pl = &plan->pl;
+    (void)hipDeviceSynchronize();
+    arena_release(pl->points);
+    arena_release(pl->tree);
+    arena_release(pl->expn);
+    delete plan;
+}
+
+axf_status axf_evaluate(axf_plan *plan, const double *S, double *phi, void *stream)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && S && phi, AXF_ERR_INVALID_ARGUMENT, "plan, S and phi must be non-NULL");
+        EvalOut o;
+        o.phi = phi;
+        run_fmm(plan->pl, plan->pl.src, plan->pl.fld, S, o, (hipStream_t)stream);
+    })
+}
+
+axf_status axf_evaluate_grad(axf_plan *plan, const double *S, double *phi, double *dphi_dr, double *dphi_dz,
+                             void *stream)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && S && phi, AXF_ERR_INVALID_ARGUMENT, "plan, S and phi must be non-NULL");
+        EvalOut o;
+        o.phi = phi;
+        o.dr = dphi_dr;
+        o.dz = dphi_dz;
+        o.mode = 1;
+        run_fmm(plan->pl, plan->pl.src, plan->pl.fld, S, o, (hipStream_t)stream);
+    })
+}
+
+axf_status axf_evaluate_direct(axf_plan *plan, const double *S, double *phi, void *stream)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && S && phi, AXF_ERR_INVALID_ARGUMENT, "plan, S and phi must be non-NULL");
+        EvalOut o;
+        o.phi = phi;
+        run_direct(plan->pl, plan->pl.src, plan->pl.fld, S, o, (hipStream_t)stream);
+    })
+}
+
+axf_status axf_adjoint(axf_plan *plan, const double *S, const double *gphi, double *gS, double *g_rsrc,
+                       double *g_zsrc, void *stream)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && gphi && gS, AXF_ERR_INVALID_ARGUMENT, "plan, gphi and gS must be non-NULL");
+        AXF_REQUIRE(!(g_rsrc || g_zsrc) || S, AXF_ERR_INVALID_ARGUMENT,
+                    "S is required for coordinate gradients");
+        EvalOut o;
+        o.phi = gS;
+        if (g_rsrc || g_zsrc) {
+            o.mode = 2;
+            o.Sdot = S;
+            o.gr = g_rsrc;
+            o.gz = g_zsrc;
+        }
+        run_fmm(plan->pl, plan->pl.fld, plan->pl.src, gphi, o, (hipStream_t)stream);
+    })
+}
+
+axf_status axf_plan_info(const axf_plan *plan, int32_t *depth, int32_t *n_modes, int32_t *order, int32_t *nrhs,
+                         int64_t *ns, int64_t *nf, double *square4, int64_t *n_near_pairs, int64_t *n_s2l_pairs,
+                         size_t *device_bytes)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
+        const Plan &pl = plan->pl;
+        if (depth) *depth = pl.d;
+        if (n_modes) *n_modes = pl.nmodes;
+        if (order) *order = pl.M;
+        if (nrhs) *nrhs = pl.nrhs;
+        if (ns) *ns = pl.src.n;
+        if (nf) *nf = pl.fld.n;
+        if (square4) {
+            square4[0] = pl.rlo;
+            square4[1] = pl.zlo;
+            square4[2] = pl.L;
+            square4[3] = pl.invL;
+        }
+        if (n_near_pairs) *n_near_pairs = pl.near_pairs;
+        if (n_s2l_pairs) *n_s2l_pairs = pl.s2l_pairs;
+        if (device_bytes) *device_bytes = pl.device_bytes;
+    })
+}
+
+axf_status axf_plan_level_info(const axf_plan *plan, int32_t level, int32_t *n_src_boxes, int32_t *n_fld_boxes)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
+        AXF_REQUIRE(level >= 2 && level <= plan->pl.d, AXF_ERR_INVALID_ARGUMENT, "level out of range");
+        if (n_src_boxes) *n_src_boxes = plan->pl.src.nocc[level];
+        if (n_fld_boxes) *n_fld_boxes = plan->pl.fld.nocc[level];
+    })
+}
+
+const char *axf_status_string(axf_status s)
+{
+    switch (s) {
+    case AXF_OK: return "AXF_OK";
+    case AXF_ERR_INVALID_ARGUMENT: return "AXF_ERR_INVALID_ARGUMENT";
+    case AXF_ERR_INVALID_GEOMETRY: return "AXF_ERR_INVALID_GEOMETRY";
+    case AXF_ERR_OUT_OF_MEMORY: return "AXF_ERR_OUT_OF_MEMORY";
+    case AXF_ERR_UNSUPPORTED: return "AXF_ERR_UNSUPPORTED";
+    case AXF_ERR_HIP: return "AXF_ERR_HIP";
+    }
+    return "AXF_ERR_UNKNOWN";
+}
+
+const char *axf_last_error(void) { return get_error(); }
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// axf_internal.hpp -- host-side structures shared by the library sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "axf.h"
+
+namespace axf {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+const char *get_error();
+
+struct Fail {
+    axf_status st;
+};
+
+#define AXF_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::axf::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+            throw ::axf::Fail{AXF_ERR_HIP};                                            \
+        }                                                                              \
+    } while (0)
+
+#define AXF_REQUIRE(cond, code, msg)                                                   \
+    do {                                                                               \
+        if (!(cond)) {                                                                 \
+            ::axf::set_error(msg);                                                     \
+            throw ::axf::Fail{code};                                                   \
+        }                                                                              \
+    } while (0)
+
+// --------------------------------------------------------------- memory
+// Device arenas are recycled through a small per-process cache so that
+// creating and destroying plans in a loop does not pay hipMalloc/hipFree.
+struct Arena {
+    char *base = nullptr;
+    size_t bytes = 0;
+    size_t used = 0;
+    int device = -1;
+    template <class T>
+    T *take(size_t count)
+    {
+        size_t off = (used + 255) & ~size_t(255);
+        size_t need = count * sizeof(T);
+        if (off + need > bytes) {
+            set_error("internal: arena overflow");
+            throw Fail{AXF_ERR_OUT_OF_MEMORY};
+        }
+        used = off + need;
+        return reinterpret_cast<T *>(base + off);
+    }
+};
+Arena arena_acquire(size_t bytes);   // throws on failure
+void arena_release(Arena &a);        // returns the block to the cache
+
+// Bytes that `take` calls will consume, for sizing an arena.
+struct Sizer {
+    size_t bytes = 0;
+    template <class T>
+    void add(size_t count)
+    {
+        bytes = ((bytes + 255) & ~size_t(255)) + count * sizeof(T);
+    }
+};
+
+// ------------------------------------------------------------------ plan
+// One point set (the sources, or the field points) sorted onto the common
+// tree.  Box ids at a level are station-major: b = ir * 2^l + iz.
+struct Side {
+    int64_t n = 0;
+    double *r = nullptr, *z = nullptr;      // sorted coordinates [n]
+    int32_t *perm = nullptr;                // sorted position -> caller index
+    int32_t *off = nullptr;                 // leaf offsets in Morton order [4^d + 1]
+    int32_t *slot[AXF_MAX_DEPTH + 1] = {};  // [4^l]: box id -> compact slot, -1 if empty
+    int32_t *box[AXF_MAX_DEPTH + 1] = {};   // [nocc]: compact slot -> box id
+    int nocc[AXF_MAX_DEPTH + 1] = {};
+    int4 *chunks = nullptr;                 // leaf work: (slot, first, count, box)
+    int nchunks = 0;
+    int max_leaf = 0;
+};
+
+struct Level {
+    int nb = 0;                // boxes per side, 2^l
+    double h = 0;              // box width
+    double2 *mom = nullptr;    // [max(nocc)][C][P] moments (z-factorial normalised)
+    double2 *loc = nullptr;    // [max(nocc)][C][P] local coefficients
+    double *tab = nullptr;     // [nb][12][n_modes][TS] S2L tables (x >= 0, outer >= inner)
+};
+
+struct Plan {
+    int device = 0;
+    axf_params p{};
+    int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
+    double rlo = 0, zlo = 0, L = 1, invL = 1;
+    double chistar = 1e300;
+    Side src, fld;
+    Level lev[AXF_MAX_DEPTH + 1];
+    double2 *Sg = nullptr;      // gathered strengths, point-major [max(ns, nf)][C]
+    double *gsum = nullptr;     // adjoint coordinate-gradient scratch
+    double *tab_scratch = nullptr;
+    Arena points, tree, expn;
+    int64_t near_pairs = 0, s2l_pairs = 0;
+    size_t device_bytes = 0;
+};
+
+// -------------------------------------------------------------- launchers
+// tree (axf_tree.hip)
+void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, const double *zf,
+                hipStream_t st);
+// tables (axf_tables.hip)
+void build_tables(Plan &pl, hipStream_t st);
+size_t table_scratch_doubles(int d, int M, int nmodes);
+// FMM passes (axf_fmm.hip).  `src` carries the strengths (gathered into
+// pl.Sg), `tgt` receives the potential.  mode: 0 = potential only,
+// 1 = potential and gradient arrays, 2 = potential and the coordinate
+// gradient contraction of the adjoint (gr, gz accumulate
+// Re(Sdot * conj(grad psi))).
+struct EvalOut {
+    double *phi = nullptr;       // complex [nrhs][nmodes][tgt.n], caller order
+    double *dr = nullptr;        // gradient outputs (mode 1)
+    double *dz = nullptr;
+    const double *Sdot = nullptr;  // mode 2: caller-order strengths at the targets
+    double *gr = nullptr, *gz = nullptr;
+    int mode = 0;
+};
+void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out,
+             hipStream_t st);
+void run_direct(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out,
+                hipStream_t st);
+
+}  // namespace axf

@@ -1,0 +1,552 @@
+// axf_tree.hip -- uniform (r, z) quadtree on the device (Algorithm 1, first
+// two steps): bounding square, depth, Morton keys, stable radix sort of both
+// point sets, leaf offsets, occupied-box slots per level and leaf work chunks.
+#include <algorithm>
+#include <cmath>
+
+#include "axf_device.hpp"
+#include "axf_internal.hpp"
+
+namespace axf {
+
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kItems = 8;                 // items per thread in scans / sort tiles
+constexpr int kTile = kBlk * kItems;      // 2048
+
+// ------------------------------------------------------------ bounding box
+__global__ void k_bbox_partial(const double *__restrict__ rs, const double *__restrict__ zs, int64_t ns,
+                               const double *__restrict__ rf, const double *__restrict__ zf, int64_t nf,
+                               double *__restrict__ part)
+{
+    double rmin = INFINITY, rmax = -INFINITY, zmin = INFINITY, zmax = -INFINITY, bad = 0;
+    int64_t n = ns + nf;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double r = i < ns ? rs[i] : rf[i - ns];
+        double z = i < ns ? zs[i] : zf[i - ns];
+        bool ok = isfinite(r) && isfinite(z) && r > 0.0;
+        if (!ok) {
+            bad += 1.0;
+            continue;
+        }
+        rmin = fmin(rmin, r);
+        rmax = fmax(rmax, r);
+        zmin = fmin(zmin, z);
+        zmax = fmax(zmax, z);
+    }
+    __shared__ double sh[5][kBlk];
+    int t = threadIdx.x;
+    sh[0][t] = rmin; sh[1][t] = rmax; sh[2][t] = zmin; sh[3][t] = zmax; sh[4][t] = bad;
+    __syncthreads();
+    for (int s = kBlk / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] = fmin(sh[0][t], sh[0][t + s]);
+            sh[1][t] = fmax(sh[1][t], sh[1][t + s]);
+            sh[2][t] = fmin(sh[2][t], sh[2][t + s]);
+            sh[3][t] = fmax(sh[3][t], sh[3][t + s]);
+            sh[4][t] += sh[4][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < 5) part[blockIdx.x * 5 + t] = sh[t][0];
+}
+
+__global__ void k_bbox_final(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    __shared__ double sh[5][kBlk];
+    int t = threadIdx.x;
+    double v[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int b = t; b < nb; b += kBlk) {
+        v[0] = fmin(v[0], part[b * 5 + 0]);
+        v[1] = fmax(v[1], part[b * 5 + 1]);
+        v[2] = fmin(v[2], part[b * 5 + 2]);
+        v[3] = fmax(v[3], part[b * 5 + 3]);
+        v[4] += part[b * 5 + 4];
+    }
+    for (int k = 0; k < 5; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int s = kBlk / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[0][t] = fmin(sh[0][t], sh[0][t + s]);
+            sh[1][t] = fmax(sh[1][t], sh[1][t + s]);
+            sh[2][t] = fmin(sh[2][t], sh[2][t + s]);
+            sh[3][t] = fmax(sh[3][t], sh[3][t + s]);
+            sh[4][t] += sh[4][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < 5) out[t] = sh[t][0];
+}
+
+// ------------------------------------------------------------------ keys
+__global__ void k_keys(const double *__restrict__ r, const double *__restrict__ z, int64_t n, double rlo,
+                       double zlo, double invL, int level, uint32_t *__restrict__ key,
+                       int32_t *__restrict__ val)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ir = box_index(r[i], rlo, invL, level);
+    int iz = box_index(z[i], zlo, invL, level);
+    key[i] = morton((uint32_t)ir, (uint32_t)iz);
+    if (val) val[i] = (int32_t)i;
+}
+
+__global__ void k_hist(const uint32_t *__restrict__ key, int64_t n, int shift, int32_t *__restrict__ hist)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&hist[key[i] >> shift], 1);
+}
+
+__global__ void k_max_int(const int32_t *__restrict__ a, int64_t n, int32_t *__restrict__ out)
+{
+    __shared__ int32_t sh[kBlk];
+    int32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, a[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kBlk / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, sh[0]);
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of int32, tiles of kTile items; block sums scanned
+// recursively.
+__global__ void k_scan_tile(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                            int32_t *__restrict__ sums)
+{
+    __shared__ int32_t sh[kBlk];
+    int t = threadIdx.x;
+    int64_t base = blockIdx.x * (int64_t)kTile + (int64_t)t * kItems;
+    int32_t v[kItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int o = 1; o < kBlk; o <<= 1) {
+        int32_t add = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    int32_t run = sh[t] - s;   // exclusive prefix of this thread
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (t == kBlk - 1 && sums) sums[blockIdx.x] = sh[t];
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ out, int64_t n, const int32_t *__restrict__ sums)
+{
+    int64_t base = blockIdx.x * (int64_t)kTile;
+    int32_t add = sums[blockIdx.x];
+    for (int k = threadIdx.x; k < kTile; k += kBlk)
+        if (base + k < n) out[base + k] += add;
+}
+
+// ------------------------------------------------------------ radix sort
+__global__ void k_rs_hist(const uint32_t *__restrict__ key, int64_t n, int shift, int nblocks,
+                          int32_t *__restrict__ counts)
+{
+    __shared__ int32_t h[256];
+    int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    int64_t base = blockIdx.x * (int64_t)kTile;
+    for (int k = t; k < kTile; k += kBlk) {
+        int64_t i = base + k;
+        if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+// Stable scatter: items are taken in order, 256 per round, ranked within the
+// wave by matching digits across ballots and across waves through LDS.
+__global__ void k_rs_scatter(const uint32_t *__restrict__ key, const int32_t *__restrict__ val, int64_t n,
+                             int shift, int nblocks, const int32_t *__restrict__ offsets,
+                             uint32_t *__restrict__ okey, int32_t *__restrict__ oval)
+{
+    __shared__ int32_t run[256];
+    __shared__ int32_t base_off[256];
+    __shared__ int32_t wcnt[kBlk / 64][256];
+    int t = threadIdx.x;
+    int w = t >> 6, lane = t & 63;
+    run[t] = 0;
+    base_off[t] = offsets[(int64_t)t * nblocks + blockIdx.x];
+    for (int k = 0; k < kBlk / 64; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+    uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int round = 0; round < kItems; ++round) {
+        int64_t i = blockIdx.x * (int64_t)kTile + (int64_t)round * kBlk + t;
+        bool act = i < n;
+        uint32_t kk = act ? key[i] : 0u;
+        int32_t vv = act ? val[i] : 0;
+        uint32_t dg = (kk >> shift) & 255u;
+        uint64_t match = __ballot(act);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1u;
+            uint64_t m = __ballot(act && bit);
+            match &= bit ? m : ~m;
+        }
+        int rank = __popcll(match & lt);
+        if (act && rank == 0) wcnt[w][dg] = __popcll(match);
+        __syncthreads();
+        if (act) {
+            int pre = run[dg];
+            for (int k = 0; k < w; ++k) pre += wcnt[k][dg];
+            int pos = base_off[dg] + pre + rank;
+            okey[pos] = kk;
+            oval[pos] = vv;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int k = 0; k < kBlk / 64; ++k) {
+            add += wcnt[k][t];
+            wcnt[k][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------- structure
+__global__ void k_gather_coords(const double *__restrict__ r, const double *__restrict__ z,
+                                const int32_t *__restrict__ perm, int64_t n, double *__restrict__ ro,
+                                double *__restrict__ zo)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t i = perm[p];
+    ro[p] = r[i];
+    zo[p] = z[i];
+}
+
+// off[m] = first sorted position with key >= m, m = 0..nleaf
+__global__ void k_offsets(const uint32_t *__restrict__ key, int64_t n, int64_t nleaf, int32_t *__restrict__ off)
+{
+    int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m > nleaf) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)key[mid] < m) lo = mid + 1;
+        else hi = mid;
+    }
+    off[m] = (int32_t)lo;
+}
+
+__device__ __forceinline__ int32_t box_count(const int32_t *__restrict__ off, int level, int depth, int b)
+{
+    int nb = 1 << level;
+    int ir = b / nb, iz = b - ir * nb;
+    uint32_t m = morton((uint32_t)ir, (uint32_t)iz);
+    int sh = 2 * (depth - level);
+    return off[(int64_t)(m + 1) << sh] - off[(int64_t)m << sh];
+}
+
+__global__ void k_flags(const int32_t *__restrict__ off, int level, int depth, int32_t *__restrict__ flag)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int nbox = 1 << (2 * level);
+    if (b >= nbox) return;
+    flag[b] = box_count(off, level, depth, b) > 0 ? 1 : 0;
+}
+
+__global__ void k_slots(const int32_t *__restrict__ flag, const int32_t *__restrict__ pre, int nbox,
+                        int32_t *__restrict__ slot, int32_t *__restrict__ box, int32_t *__restrict__ count)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    if (flag[b]) {
+        slot[b] = pre[b];
+        box[pre[b]] = b;
+    } else {
+        slot[b] = -1;
+    }
+    if (b == nbox - 1) *count = pre[b] + flag[b];
+}
+
+__global__ void k_chunk_count(const int32_t *__restrict__ off, const int32_t *__restrict__ box, int nocc,
+                              int depth, int32_t *__restrict__ nch, int32_t *__restrict__ maxleaf)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nocc) return;
+    int c = box_count(off, depth, depth, box[k]);
+    nch[k] = (c + 63) / 64;
+    atomicMax(maxleaf, c);
+}
+
+__global__ void k_chunk_fill(const int32_t *__restrict__ off, const int32_t *__restrict__ box, int nocc,
+                             int depth, const int32_t *__restrict__ pre, int4 *__restrict__ chunks,
+                             int32_t *__restrict__ total)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nocc) return;
+    int b = box[k];
+    int nb = 1 << depth;
+    int ir = b / nb, iz = b - ir * nb;
+    uint32_t m = morton((uint32_t)ir, (uint32_t)iz);
+    int first = off[m], cnt = off[m + 1] - first;
+    int c0 = pre[k];
+    for (int j = 0; j * 64 < cnt; ++j)
+        chunks[c0 + j] = make_int4(k, first + j * 64, min(64, cnt - j * 64), b);
+    if (k == nocc - 1) *total = c0 + (cnt + 63) / 64;
+}
+
+inline int nblk(int64_t n, int b = kBlk) { return (int)((n + b - 1) / b); }
+
+// Recursive exclusive scan; tmp must hold scan_tmp_ints(n) ints.
+int64_t scan_tmp_ints(int64_t n)
+{
+    int64_t tot = 0;
+    while (n > 1) {
+        int64_t nb = (n + kTile - 1) / kTile;
+        tot += nb + 64;
+        n = nb;
+    }
+    return tot + 64;
+}
+
+void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t nb = (n + kTile - 1) / kTile;
+    if (nb == 1) {
+        k_scan_tile<<<1, kBlk, 0, st>>>(in, out, n, nullptr);
+        return;
+    }
+    int32_t *sums = tmp;
+    int32_t *rest = tmp + nb + 64;
+    k_scan_tile<<<(int)nb, kBlk, 0, st>>>(in, out, n, sums);
+    scan_excl(sums, sums, nb, rest, st);
+    k_scan_add<<<(int)nb, kBlk, 0, st>>>(out, n, sums);
+}
+
+struct SortBufs {
+    uint32_t *k0, *k1;
+    int32_t *v0, *v1;
+    int32_t *counts;
+    int32_t *tmp;
+};
+
+// Stable LSD radix sort of (key, val) on the low `bits` bits; result in k0/v0.
+void radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
+{
+    int nblocks = (int)((n + kTile - 1) / kTile);
+    uint32_t *ka = b.k0, *kb = b.k1;
+    int32_t *va = b.v0, *vb = b.v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        k_rs_hist<<<nblocks, kBlk, 0, st>>>(ka, n, shift, nblocks, b.counts);
+        scan_excl(b.counts, b.counts, (int64_t)256 * nblocks, b.tmp, st);
+        k_rs_scatter<<<nblocks, kBlk, 0, st>>>(ka, va, n, shift, nblocks, b.counts, kb, vb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != b.k0) {
+        AXF_HIP(hipMemcpyAsync(b.k0, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+        AXF_HIP(hipMemcpyAsync(b.v0, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
+}
+
+struct PointScratch {
+    uint32_t *key11;      // keys at the deepest level (auto depth only)
+    SortBufs sb;
+};
+
+}  // namespace
+
+void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, const double *zf,
+                hipStream_t st)
+{
+    const int64_t ns = pl.src.n, nf = pl.fld.n;
+    const int64_t nmax = std::max(ns, nf);
+    const bool autod = pl.p.depth == 0;
+
+    // ---- point arena: sorted coordinates, permutations, gathered strengths, sort scratch
+    Sizer sz;
+    sz.add<double>(5 * 1024 + 8);              // bbox partials + result
+    for (int64_t n : {ns, nf}) {
+        sz.add<double>(n);
+        sz.add<double>(n);
+        sz.add<int32_t>(n);
+    }
+    sz.add<double2>((size_t)nmax * pl.C);      // gathered strengths
+    sz.add<double>(2 * (size_t)ns);            // adjoint coordinate-gradient scratch
+    const int64_t nb11 = autod ? ((int64_t)1 << (2 * AXF_MAX_DEPTH)) : 0;
+    if (autod) {
+        sz.add<uint32_t>(ns);
+        sz.add<uint32_t>(nf);
+        sz.add<int32_t>(nb11);
+        sz.add<int32_t>(nb11);
+    }
+    sz.add<uint32_t>(nmax);
+    sz.add<uint32_t>(nmax);
+    sz.add<int32_t>(nmax);
+    sz.add<int32_t>(nmax);
+    int64_t cnt_ints = 256 * ((nmax + kTile - 1) / kTile);
+    sz.add<int32_t>(cnt_ints);
+    int64_t tmp_ints = std::max<int64_t>(scan_tmp_ints(cnt_ints), scan_tmp_ints((int64_t)1 << (2 * AXF_MAX_DEPTH)));
+    sz.add<int32_t>(tmp_ints);
+    sz.add<int32_t>(64);
+    pl.points = arena_acquire(sz.bytes + 4096);
+    Arena &A = pl.points;
+    double *bb = A.take<double>(5 * 1024 + 8);
+    pl.src.r = A.take<double>(ns);
+    pl.src.z = A.take<double>(ns);
+    pl.src.perm = A.take<int32_t>(ns);
+    pl.fld.r = A.take<double>(nf);
+    pl.fld.z = A.take<double>(nf);
+    pl.fld.perm = A.take<int32_t>(nf);
+    pl.Sg = A.take<double2>((size_t)nmax * pl.C);
+    pl.gsum = A.take<double>(2 * (size_t)ns);
+    uint32_t *k11s = nullptr, *k11f = nullptr;
+    int32_t *hs = nullptr, *hf = nullptr;
+    if (autod) {
+        k11s = A.take<uint32_t>(ns);
+        k11f = A.take<uint32_t>(nf);
+        hs = A.take<int32_t>(nb11);
+        hf = A.take<int32_t>(nb11);
+    }
+    SortBufs sb;
+    sb.k0 = A.take<uint32_t>(nmax);
+    sb.k1 = A.take<uint32_t>(nmax);
+    sb.v0 = A.take<int32_t>(nmax);
+    sb.v1 = A.take<int32_t>(nmax);
+    sb.counts = A.take<int32_t>(cnt_ints);
+    sb.tmp = A.take<int32_t>(tmp_ints);
+    int32_t *small = A.take<int32_t>(64);
+
+    // ---- bounding square and validation
+    int nbb = std::min<int64_t>(1024, std::max<int64_t>(1, (ns + nf + kBlk - 1) / kBlk));
+    k_bbox_partial<<<nbb, kBlk, 0, st>>>(rs, zs, ns, rf, zf, nf, bb);
+    k_bbox_final<<<1, kBlk, 0, st>>>(bb, nbb, bb + 5 * 1024);
+    double box[5];
+    AXF_HIP(hipMemcpyAsync(box, bb + 5 * 1024, sizeof(box), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipStreamSynchronize(st));
+    AXF_REQUIRE(box[4] == 0.0, AXF_ERR_INVALID_GEOMETRY,
+                "a coordinate is not finite or a ring radius is <= 0");
+    pl.rlo = box[0];
+    pl.zlo = box[2];
+    double ext = std::max(box[1] - box[0], box[3] - box[2]);
+    pl.L = ext > 0.0 ? ext : 1.0;
+    pl.invL = 1.0 / pl.L;
+
+    // ---- depth
+    int d = pl.p.depth;
+    if (autod) {
+        k_keys<<<nblk(ns), kBlk, 0, st>>>(rs, zs, ns, pl.rlo, pl.zlo, pl.invL, AXF_MAX_DEPTH, k11s, nullptr);
+        k_keys<<<nblk(nf), kBlk, 0, st>>>(rf, zf, nf, pl.rlo, pl.zlo, pl.invL, AXF_MAX_DEPTH, k11f, nullptr);
+        auto max_count = [&](int dd) {
+            int64_t nl = (int64_t)1 << (2 * dd);
+            AXF_HIP(hipMemsetAsync(hs, 0, nl * sizeof(int32_t), st));
+            AXF_HIP(hipMemsetAsync(hf, 0, nl * sizeof(int32_t), st));
+            AXF_HIP(hipMemsetAsync(small, 0, sizeof(int32_t), st));
+            int sh = 2 * (AXF_MAX_DEPTH - dd);
+            k_hist<<<nblk(ns), kBlk, 0, st>>>(k11s, ns, sh, hs);
+            k_hist<<<nblk(nf), kBlk, 0, st>>>(k11f, nf, sh, hf);
+            int g = (int)std::min<int64_t>(1024, (nl + kBlk - 1) / kBlk);
+            k_max_int<<<g, kBlk, 0, st>>>(hs, nl, small);
+            k_max_int<<<g, kBlk, 0, st>>>(hf, nl, small);
+            int32_t mx = 0;
+            AXF_HIP(hipMemcpyAsync(&mx, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            AXF_HIP(hipStreamSynchronize(st));
+            return (int)mx;
+        };
+        double est = std::log((double)nmax / std::max(1, pl.p.max_leaf)) / std::log(4.0);
+        d = std::max(2, std::min(AXF_MAX_DEPTH, (int)std::ceil(est)));
+        if (max_count(d) <= pl.p.max_leaf) {
+            while (d > 2 && max_count(d - 1) <= pl.p.max_leaf) --d;
+        } else {
+            while (d < AXF_MAX_DEPTH && max_count(d) > pl.p.max_leaf) ++d;
+        }
+    }
+    pl.d = d;
+
+    // ---- per side: keys at depth d, sort, gather coordinates
+    const int bits = 2 * d;
+    struct In {
+        Side *s;
+        const double *r, *z;
+    } ins[2] = {{&pl.src, rs, zs}, {&pl.fld, rf, zf}};
+    // structure arena sized by depth
+    const int64_t nleaf = (int64_t)1 << (2 * d);
+    Sizer ss;
+    for (int side = 0; side < 2; ++side) {
+        int64_t n = ins[side].s->n;
+        ss.add<int32_t>(nleaf + 1);
+        for (int l = 2; l <= d; ++l) {
+            ss.add<int32_t>((int64_t)1 << (2 * l));
+            ss.add<int32_t>(std::min<int64_t>((int64_t)1 << (2 * l), n));
+        }
+        int64_t nocc_max = std::min<int64_t>(nleaf, n);
+        ss.add<int4>(nocc_max + n / 64 + 1);
+    }
+    ss.add<int32_t>(nleaf + 1);   // flags / chunk counts
+    ss.add<int32_t>(nleaf + 1);   // prefix
+    pl.tree = arena_acquire(ss.bytes + 4096);
+    Arena &T = pl.tree;
+    for (int side = 0; side < 2; ++side) {
+        Side &s = *ins[side].s;
+        s.off = T.take<int32_t>(nleaf + 1);
+        for (int l = 2; l <= d; ++l) {
+            s.slot[l] = T.take<int32_t>((int64_t)1 << (2 * l));
+            s.box[l] = T.take<int32_t>(std::min<int64_t>((int64_t)1 << (2 * l), s.n));
+        }
+        s.chunks = T.take<int4>(std::min<int64_t>(nleaf, s.n) + s.n / 64 + 1);
+    }
+    int32_t *flag = T.take<int32_t>(nleaf + 1);
+    int32_t *pre = T.take<int32_t>(nleaf + 1);
+
+    // small[] layout: [0..1] maxleaf per side, [2..3] nchunks, [4 + 2*l + side] nocc
+    AXF_HIP(hipMemsetAsync(small, 0, 64 * sizeof(int32_t), st));
+    for (int side = 0; side < 2; ++side) {
+        Side &s = *ins[side].s;
+        int64_t n = s.n;
+        k_keys<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, n, pl.rlo, pl.zlo, pl.invL, d, sb.k0, sb.v0);
+        radix_sort(sb, n, bits, st);
+        AXF_HIP(hipMemcpyAsync(s.perm, sb.v0, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        k_gather_coords<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, s.perm, n, s.r, s.z);
+        k_offsets<<<nblk(nleaf + 1), kBlk, 0, st>>>(sb.k0, n, nleaf, s.off);
+        for (int l = 2; l <= d; ++l) {
+            int nbox = 1 << (2 * l);
+            k_flags<<<nblk(nbox), kBlk, 0, st>>>(s.off, l, d, flag);
+            scan_excl(flag, pre, nbox, sb.tmp, st);
+            k_slots<<<nblk(nbox), kBlk, 0, st>>>(flag, pre, nbox, s.slot[l], s.box[l], small + 4 + 2 * l + side);
+        }
+    }
+    // occupancy counts are needed to size the leaf work lists
+    int32_t h_small[64];
+    AXF_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipStreamSynchronize(st));
+    for (int side = 0; side < 2; ++side) {
+        Side &s = *ins[side].s;
+        for (int l = 2; l <= d; ++l) s.nocc[l] = h_small[4 + 2 * l + side];
+        int nocc = s.nocc[d];
+        k_chunk_count<<<nblk(nocc), kBlk, 0, st>>>(s.off, s.box[d], nocc, d, flag, small + side);
+        scan_excl(flag, pre, nocc, sb.tmp, st);
+        k_chunk_fill<<<nblk(nocc), kBlk, 0, st>>>(s.off, s.box[d], nocc, d, pre, s.chunks, small + 2 + side);
+    }
+    AXF_HIP(hipMemcpyAsync(h_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipStreamSynchronize(st));
+    pl.src.max_leaf = h_small[0];
+    pl.fld.max_leaf = h_small[1];
+    pl.src.nchunks = h_small[2];
+    pl.fld.nchunks = h_small[3];
+}
+
+}  // namespace axf
