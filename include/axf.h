@@ -141,6 +141,32 @@ axf_status axf_plan_info(const axf_plan *plan, int32_t *depth, int32_t *n_modes,
 axf_status axf_plan_level_info(const axf_plan *plan, int32_t level,
                                int32_t *n_src_boxes, int32_t *n_fld_boxes);
 
+/* Phase timing.  When enabled, the library records HIP events on the calling
+ * stream around every pass of axf_evaluate / axf_evaluate_grad /
+ * axf_evaluate_direct / axf_adjoint and accumulates their durations
+ * (milliseconds) and launch counts per phase until read.  Reading
+ * synchronises on the recorded events and resets the accumulators.
+ * Phases: see AXF_PHASE_*. */
+enum {
+    AXF_PHASE_GATHER = 0,  /* strengths into tree order                      */
+    AXF_PHASE_P2M = 1,     /* leaf moments, eq. analysis:moments             */
+    AXF_PHASE_M2M = 2,     /* upward pass, eq. analysis:shift                */
+    AXF_PHASE_S2L = 3,     /* downward pass: S2L + local shift               */
+    AXF_PHASE_LEAF = 4,    /* local expansion + near field at the leaves     */
+    AXF_PHASE_DIRECT = 5,  /* direct modal sum                               */
+    AXF_NUM_PHASES = 6
+};
+axf_status axf_plan_set_timing(axf_plan *plan, int32_t enable);
+axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHASES] */,
+                                int32_t *launches /* host [AXF_NUM_PHASES] */);
+
+/* Algorithmic work of one evaluation (host outputs, any may be NULL):
+ * near-field ring pairs, S2L box pairs, and the floating-point operation
+ * counts of the model documented with the benchmark (FP64 flops per phase,
+ * [AXF_NUM_PHASES]). */
+axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs,
+                         double *flops /* host [AXF_NUM_PHASES] */);
+
 /* ---------------------------------------------------------------------- */
 /* Batched launches: many independent problems (uneven sizes, own points,
  * own right-hand-side counts; common n_modes and order) evaluated by one

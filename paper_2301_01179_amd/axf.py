@@ -24,7 +24,10 @@ EXPORTED = [
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
     "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
+    "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work",
 ]
+
+PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct"]
 
 
 class AxfError(RuntimeError):
@@ -80,9 +83,13 @@ def load_library(path: str = LIB_PATH):
     lib.axf_status_string.restype = ctypes.c_char_p
     lib.axf_last_error.argtypes = []
     lib.axf_last_error.restype = ctypes.c_char_p
+    lib.axf_plan_set_timing.argtypes = [vp, i32]
+    lib.axf_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i32)]
+    lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(ctypes.c_double)]
     for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
-                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth"):
+                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
+                 "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -163,6 +170,24 @@ class Plan:
         return {"depth": d.value, "n_modes": nm.value, "order": m.value, "nrhs": nr.value,
                 "ns": ns.value, "nf": nf.value, "square": tuple(sq), "near_pairs": near.value,
                 "s2l_pairs": s2l.value, "device_bytes": nbytes.value, "levels": levels}
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib.axf_plan_set_timing(self._h, 1 if enable else 0), "axf_plan_set_timing")
+
+    def read_timing(self) -> dict:
+        """Per-phase milliseconds and launch counts since the last read."""
+        ms = (ctypes.c_double * len(PHASES))()
+        n = (ctypes.c_int32 * len(PHASES))()
+        _check(_lib.axf_plan_read_timing(self._h, ms, n), "axf_plan_read_timing")
+        return {p: (ms[i], n[i]) for i, p in enumerate(PHASES)}
+
+    def work(self) -> dict:
+        """Near pairs, S2L box pairs and the per-phase FP64 flop model."""
+        near, s2l = ctypes.c_int64(), ctypes.c_int64()
+        fl = (ctypes.c_double * len(PHASES))()
+        _check(_lib.axf_plan_work(self._h, ctypes.byref(near), ctypes.byref(s2l), fl), "axf_plan_work")
+        return {"near_pairs": near.value, "s2l_pairs": s2l.value,
+                "flops": {p: fl[i] for i, p in enumerate(PHASES)}}
 
     # ------------------------------------------------------- evaluation
     def _strengths(self, S, n):

@@ -82,14 +82,52 @@ void arena_release(Arena &a)
     a = Arena();
 }
 
-static void plan_free(Plan *pl)
+hipEvent_t event_get(Plan &pl)
+{
+    if (!pl.spare_events.empty()) {
+        hipEvent_t e = pl.spare_events.back();
+        pl.spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    AXF_HIP(hipEventCreate(&e));
+    return e;
+}
+
+PhaseTimer::PhaseTimer(Plan &p, hipStream_t s, int ph) : pl(p), st(s), phase(ph)
+{
+    if (!pl.timing || phase < 0) return;
+    a = event_get(pl);
+    b = event_get(pl);
+    AXF_HIP(hipEventRecord(a, st));
+}
+
+PhaseTimer::~PhaseTimer()
+{
+    if (!a) return;
+    if (hipEventRecord(b, st) == hipSuccess) pl.marks.push_back({phase, a, b});
+}
+
+static void release_events(Plan *pl)
+{
+    for (auto &m : pl->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (auto e : pl->spare_events) (void)hipEventDestroy(e);
+    pl->marks.clear();
+    pl->spare_events.clear();
+}
+
+static void plan_release(Plan *pl)
 {
     if (!pl) return;
     (void)hipDeviceSynchronize();
+    release_events(pl);
     arena_release(pl->points);
     arena_release(pl->tree);
     arena_release(pl->expn);
-    delete pl;
+    arena_release(pl->tilemem);
 }
 
 static void validate_params(const axf_params *p)
@@ -119,9 +157,12 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     pl.C = p.n_modes * p.nrhs;
     pl.TS = (p.order + 1) * (p.order + 1) * (p.order + 1);
     pl.chistar = forward_chi_limit(p.n_modes);
+    pl.nmb = mode_bucket(p.n_modes);
+    pl.Cs = pl.nmb * p.nrhs;
     pl.src.n = ns;
     pl.fld.n = nf;
     build_tree(pl, rs, zs, rf, zf, st);
+    build_tiles(pl, st);
 
     // expansion arena: moments, locals, tables, table scratch
     const int d = pl.d;
@@ -147,7 +188,7 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].tab = tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
     pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     build_tables(pl, st);
-    pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes;
+    pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes;
 }
 
 }  // namespace axf
@@ -158,9 +199,9 @@ struct axf_plan {
     Plan pl;
 };
 
-#define AXF_TRY(body)                                       \
+#define AXF_TRY(...)                                        \
     try {                                                   \
-        body;                                               \
+        __VA_ARGS__;                                        \
         return AXF_OK;                                      \
     } catch (const Fail &f) {                               \
         return f.st;                                        \
@@ -192,7 +233,10 @@ axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r
         *out_plan = h;
         return AXF_OK;
     } catch (const Fail &f) {
-        if (h) plan_free(&h->pl), h = nullptr;
+        if (h) {
+            plan_release(&h->pl);
+            delete h;
+        }
         return f.st;
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
@@ -203,11 +247,7 @@ axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r
 void axf_plan_destroy(axf_plan *plan)
 {
     if (!plan) return;
-    Plan *pl = &plan->pl;
-    (void)hipDeviceSynchronize();
-    arena_release(pl->points);
-    arena_release(pl->tree);
-    arena_release(pl->expn);
+    plan_release(&plan->pl);
     delete plan;
 }
 
@@ -296,6 +336,66 @@ axf_status axf_plan_level_info(const axf_plan *plan, int32_t level, int32_t *n_s
         AXF_REQUIRE(level >= 2 && level <= plan->pl.d, AXF_ERR_INVALID_ARGUMENT, "level out of range");
         if (n_src_boxes) *n_src_boxes = plan->pl.src.nocc[level];
         if (n_fld_boxes) *n_fld_boxes = plan->pl.fld.nocc[level];
+    })
+}
+
+axf_status axf_plan_set_timing(axf_plan *plan, int32_t enable)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
+        plan->pl.timing = enable != 0;
+    })
+}
+
+axf_status axf_plan_read_timing(axf_plan *plan, double *ms, int32_t *launches)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && ms, AXF_ERR_INVALID_ARGUMENT, "plan and ms must be non-NULL");
+        Plan &pl = plan->pl;
+        for (int i = 0; i < AXF_NUM_PHASES; ++i) {
+            ms[i] = 0.0;
+            if (launches) launches[i] = 0;
+        }
+        for (auto &m : pl.marks) {
+            AXF_HIP(hipEventSynchronize(m.b));
+            float t = 0.f;
+            AXF_HIP(hipEventElapsedTime(&t, m.a, m.b));
+            ms[m.phase] += t;
+            if (launches) launches[m.phase] += 1;
+            pl.spare_events.push_back(m.a);
+            pl.spare_events.push_back(m.b);
+        }
+        pl.marks.clear();
+    })
+}
+
+axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs, double *flops)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
+        const Plan &pl = plan->pl;
+        if (near_pairs) *near_pairs = pl.near_pairs;
+        if (s2l_pairs) *s2l_pairs = pl.s2l_pairs;
+        if (flops) {
+            // FP64 operation model (fma = 2): a near-field pair costs a fixed
+            // 60 flops of geometry and AGM, 3 per mode of recursion and 4 per
+            // mode and right-hand side of complex accumulation.
+            const double P = pl.P, C = pl.C, Nm = pl.nmodes, R = pl.nrhs;
+            const double M = pl.M;
+            const double c4 = (M + 1) * (M + 2) * (M + 3) * (M + 4) / 24.0;   // C(M+4, 4)
+            double pair = 60.0 + 3.0 * Nm + 4.0 * Nm * R;
+            double nbox_up = 0, nbox_down = 0;
+            for (int l = 3; l <= pl.d; ++l) {
+                nbox_up += pl.src.nocc[l];
+                nbox_down += pl.fld.nocc[l];
+            }
+            flops[AXF_PHASE_GATHER] = 0.0;
+            flops[AXF_PHASE_P2M] = (double)pl.src.n * (4.0 * P * C + 2.0 * P);
+            flops[AXF_PHASE_M2M] = nbox_up * C * c4 * 4.0;
+            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0 + nbox_down * C * c4 * 4.0;
+            flops[AXF_PHASE_LEAF] = (double)pl.near_pairs * pair + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
+            flops[AXF_PHASE_DIRECT] = (double)pl.src.n * (double)pl.fld.n * pair;
+        }
     })
 }
 

@@ -131,6 +131,62 @@ __device__ __forceinline__ void green_modes(double rm2, double rp2, double rr, d
     }
 }
 
+// sqrt and reciprocal for positive normal arguments: hardware estimate
+// refined by Newton steps (Goldschmidt form for the square root); within a
+// few ulp, without the range scaling of the IEEE-rounded library versions.
+__device__ __forceinline__ double fast_sqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// Start values of one pair: G^(0) = 1 / (2 AGM(rho+, rho-)) and
+// G^(1) = G^(0) (1 / (2 r r1)) sum_{n>=1} 2^(n-1) c_n^2 (from E/K by the AGM).
+struct PairStart {
+    double g0, g1, chi, dchi;
+};
+
+__device__ __forceinline__ PairStart pair_start(double rm2, double rp2, double rr, double inv_rr)
+{
+    double rp = fast_sqrt(rp2), rm = fast_sqrt(rm2);
+    double a = rp, b = rm;
+    double c = 2.0 * rr * fast_rcp(rp + rm);
+    double csum = c * c, w = 1.0;
+    for (int it = 0; it < 48; ++it) {
+        double an = 0.5 * (a + b);
+        b = fast_sqrt(a * b);
+        a = an;
+        if (c <= 0x1p-30 * a) break;
+        c = 0.5 * (a - b);
+        w *= 2.0;
+        csum = fma(w * c, c, csum);
+    }
+    PairStart ps;
+    ps.g0 = 0.5 * fast_rcp(a);
+    ps.g1 = ps.g0 * csum * 0.5 * inv_rr;
+    ps.chi = (rp2 + rm2) * 0.25 * inv_rr;
+    ps.dchi = rm2 * 0.5 * inv_rr;
+    return ps;
+}
+
 // Spread the low 11 bits of v to the even bit positions.
 __host__ __device__ __forceinline__ uint32_t spread_bits(uint32_t v)
 {

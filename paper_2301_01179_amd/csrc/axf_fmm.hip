@@ -26,22 +26,23 @@ struct SideView {     // device-side view of a Side
 };
 
 // ---------------------------------------------------------------- gather
+// Strengths into tree order, point-major with Cs = nmb * nrhs channels per
+// point (channel n * nrhs + q; modes nmodes..nmb-1 are zero padding).
 __global__ void k_gather(const double2 *__restrict__ S, const int32_t *__restrict__ perm, int64_t n,
-                         int nmodes, int nrhs, double2 *__restrict__ Sg)
+                         int nmodes, int nrhs, int Cs, double2 *__restrict__ Sg)
 {
-    int C = nmodes * nrhs;
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= n * C) return;
-    int64_t p = e / C;
-    int c = (int)(e - p * C);
+    if (e >= n * Cs) return;
+    int64_t p = e / Cs;
+    int c = (int)(e - p * Cs);
     int nn = c / nrhs, q = c - nn * nrhs;
-    Sg[e] = S[((int64_t)q * nmodes + nn) * n + perm[p]];
+    Sg[e] = nn < nmodes ? S[((int64_t)q * nmodes + nn) * n + perm[p]] : make_double2(0.0, 0.0);
 }
 
 // ------------------------------------------------------------------- P2M
 constexpr int kP2MChunk = 32;
-__global__ __launch_bounds__(256) void k_p2m(int M, int C, int depth, double rlo, double zlo, double invh,
-                                            SideView sv, const int32_t *__restrict__ boxes,
+__global__ __launch_bounds__(256) void k_p2m(int M, int C, int Cs, int depth, double rlo, double zlo,
+                                            double invh, SideView sv, const int32_t *__restrict__ boxes,
                                             const double2 *__restrict__ Sg, double2 *__restrict__ mom)
 {
     __shared__ double pr[kP2MChunk][AXF_MAX_ORDER + 1];
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void k_p2m(int M, int C, int depth, double rlo
                     double2 a = acc[u];
                     for (int s = 0; s < ns; ++s) {
                         double w = pr[s][i] * pz[s][j];
-                        double2 sv2 = Sg[(int64_t)(s0 + s) * C + c];
+                        double2 sv2 = Sg[(int64_t)(s0 + s) * Cs + c];
                         a.x += w * sv2.x;
                         a.y += w * sv2.y;
                     }
@@ -323,22 +324,422 @@ __global__ __launch_bounds__(256) void k_s2l(int M, int nmodes, int nrhs, int le
     }
 }
 
+// ------------------------------------------------------- S2L, tiled form
+// One wave per (tile, channel).  A tile is up to TB occupied target boxes of
+// one radial station with the same z parity, so that every box of the tile
+// has the same interaction-list offsets (dr, dz) and therefore, for each
+// offset, the same operator: one table, one orientation.  Lane L owns the
+// outputs (k, l0 .. l0+LB-1) of all TB boxes; for each input moment (i, j)
+// the table values T[k][i][j+l] of the lane's outputs form a window that
+// slides by one entry per j (Hankel structure), so each step loads one table
+// value and does 2 LB TB FMAs on moments broadcast from LDS.  The forward
+// sign (-1)^(j+l) is split into (-1)^j on the staged moments and (-1)^l on
+// the accumulators.
+template <int LB, int TB>
+__global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
+                                                 const int4 *__restrict__ tiles,      // station, parity, first, count
+                                                 const int32_t *__restrict__ tslots,  // target slots of the tiles
+                                                 const int32_t *__restrict__ tbox,    // slot -> box id (targets)
+                                                 const int32_t *__restrict__ tslot_parent,
+                                                 const double2 *__restrict__ ploc,
+                                                 const int32_t *__restrict__ sslot,
+                                                 const double2 *__restrict__ mom,
+                                                 const double *__restrict__ tab,
+                                                 double2 *__restrict__ loc)
+{
+    extern __shared__ double2 ms[];          // [TB][P] staged moments
+    __shared__ double lcoef[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
+    __shared__ double invfact[AXF_MAX_ORDER + 1];
+    const int P = (M + 1) * (M + 2) / 2;
+    const int C = nmodes * nrhs;
+    const int ti = blockIdx.x / C, c = blockIdx.x - (blockIdx.x / C) * C;
+    const int n = c / nrhs;
+    const int4 tl = tiles[ti];
+    const int station = tl.x, nbx = tl.w;
+    const int nb = 1 << level;
+    const int lane = threadIdx.x;
+
+    if (lane <= M) {
+        double f = 1.0;
+        for (int t = 2; t <= lane; ++t) f *= t;
+        invfact[lane] = 1.0 / f;
+    }
+    for (int e = lane; e < 2 * (M + 1) * (M + 1); e += 64) {
+        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
+        int i = rem / (M + 1), q = rem - i * (M + 1);
+        double d = sg ? 0.25 : -0.25, v = 0.0;
+        if (i + q <= M) {
+            double bin = 1.0, pw = 1.0;
+            for (int t = 0; t < q; ++t) {
+                bin = bin * (i + q - t) / (t + 1.0);
+                pw *= d;
+            }
+            v = bin * pw * ldexp(1.0, -i);
+        }
+        lcoef[sg][i][q] = v;
+    }
+    // this lane's outputs: row k, columns l0 .. l0 + LB - 1
+    int k = 0, l0 = 0, acc_lane = lane;
+    bool live = false;
+    for (int kk = 0; kk <= M; ++kk) {
+        int nblk = (M + 1 - kk + LB - 1) / LB;
+        if (acc_lane < nblk) {
+            k = kk;
+            l0 = acc_lane * LB;
+            live = true;
+            break;
+        }
+        acc_lane -= nblk;
+    }
+    int zb[TB], sl[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+        sl[b] = b < nbx ? tslots[tl.z + b] : -1;
+        int bid = sl[b] >= 0 ? tbox[sl[b]] : 0;
+        zb[b] = bid - (bid / nb) * nb;
+    }
+    double2 acc[LB][TB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u)
+#pragma unroll
+        for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(0.0, 0.0);
+
+    const int par = tl.y;                       // z parity of the tile
+    const int dr0 = -2 - (station & 1), dz0 = -2 - par;
+    const double *tab_n = tab + (size_t)n * TS;
+    for (int dr = dr0; dr < dr0 + 6; ++dr) {
+        const int jr = station + dr;
+        if (jr < 0 || jr >= nb) continue;
+        for (int dz = dz0; dz < dz0 + 6; ++dz) {
+            if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) continue;
+            int ss[TB];
+            bool any = false;
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                int jz = zb[b] + dz;
+                ss[b] = (sl[b] >= 0 && jz >= 0 && jz < nb) ? sslot[jr * nb + jz] : -1;
+                any |= ss[b] >= 0;
+            }
+            if (!any) continue;
+            const bool outward = dr <= 0;               // target radius >= source radius
+            const bool fwd = dz <= 0;                   // z_target >= z_source
+            const int inner = outward ? jr : station;
+            const int adr = outward ? -dr : dr, adz = dz < 0 ? -dz : dz;
+            const double *T = tab_n + ((size_t)inner * 12 + geom_slot(adr, adz)) * nmodes * (size_t)TS;
+            __syncthreads();
+            for (int e = lane; e < TB * P; e += 64) {
+                int b = e / P, p = e - b * P;
+                double2 v = make_double2(0.0, 0.0);
+                if (ss[b] >= 0) v = mom[((int64_t)ss[b] * C + c) * P + p];
+                if (fwd) {
+                    int i = 0, q = p;
+                    while (q >= M + 1 - i) {
+                        q -= M + 1 - i;
+                        ++i;
+                    }
+                    if (q & 1) v = make_double2(-v.x, -v.y);
+                }
+                ms[e] = v;
+            }
+            __syncthreads();
+            if (fwd) {
+#pragma unroll
+                for (int u = 0; u < LB; ++u)
+                    if ((l0 + u) & 1)
+#pragma unroll
+                        for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
+            }
+            if (live) {
+                int pbase = 0;
+                for (int i = 0; i <= M; ++i) {
+                    const int a_ = outward ? k : i, b_ = outward ? i : k;
+                    const double *row = T + table_row(M, a_, b_);
+                    const int rl = 2 * M - a_ - b_;     // last valid c
+                    double w[LB];
+#pragma unroll
+                    for (int u = 0; u < LB; ++u) w[u] = row[min(l0 + u, rl)];
+                    const int jn = M - i;
+                    for (int j = 0; j <= jn; ++j) {
+#pragma unroll
+                        for (int b = 0; b < TB; ++b) {
+                            const double2 sv = ms[b * P + pbase + j];
+#pragma unroll
+                            for (int u = 0; u < LB; ++u) {
+                                acc[u][b].x = fma(w[u], sv.x, acc[u][b].x);
+                                acc[u][b].y = fma(w[u], sv.y, acc[u][b].y);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u + 1 < LB; ++u) w[u] = w[u + 1];
+                        w[LB - 1] = row[min(j + 1 + l0 + LB - 1, rl)];
+                    }
+                    pbase += jn + 1;
+                }
+            }
+            if (fwd) {
+#pragma unroll
+                for (int u = 0; u < LB; ++u)
+                    if ((l0 + u) & 1)
+#pragma unroll
+                        for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
+            }
+        }
+    }
+    __syncthreads();
+    // write: (-1)^l / l! * acc + parent's local shifted (eq. analysis:l2l)
+    if (!live) return;
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+        if (sl[b] < 0) continue;
+        const int bid = tbox[sl[b]];
+        const int ir = bid / nb, iz = bid - ir * nb;
+        int pslot = -1;
+        if (level > 2) pslot = tslot_parent[(ir >> 1) * (nb >> 1) + (iz >> 1)];
+        const int sr = ir & 1, sz = iz & 1;
+        const double2 *pl = pslot >= 0 ? ploc + ((int64_t)pslot * C + c) * P : nullptr;
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int ll = l0 + u;
+            if (ll > M - k) continue;
+            const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
+            double2 v = make_double2(f * acc[u][b].x, f * acc[u][b].y);
+            if (pl) {
+                for (int a = 0; k + a <= M; ++a) {
+                    const double fa = lcoef[sr][k][a];
+                    for (int c2 = 0; k + a + ll + c2 <= M; ++c2) {
+                        const double wgt = fa * lcoef[sz][ll][c2];
+                        const double2 x = pl[tri_index(M, k + a, ll + c2)];
+                        v.x = fma(wgt, x.x, v.x);
+                        v.y = fma(wgt, x.y, v.y);
+                    }
+                }
+            }
+            loc[((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll)] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ pair sums
+// Accumulators of one lane: potential, and for MODE != 0 the r- and
+// x-derivatives (App. A, first-derivative starting formulas).
+template <int NMB, int MODE>
+struct Acc {
+    double ar[NMB], ai[NMB];
+    double rr_[MODE ? NMB : 1], ri_[MODE ? NMB : 1], zr_[MODE ? NMB : 1], zi_[MODE ? NMB : 1];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int n = 0; n < NMB; ++n) {
+            ar[n] = ai[n] = 0.0;
+            if constexpr (MODE != 0) rr_[n] = ri_[n] = zr_[n] = zi_[n] = 0.0;
+        }
+    }
+};
+
+// Adds S_s^(n) G^(n)(r, r1, x) for n < nmodes of one pair per lane.  All
+// lanes of the wave call it together (the backward recursion runs a
+// wave-wide number of steps).  `use` = false lanes contribute nothing.
+// Forward recursion (chi < chistar) streams straight into the accumulators;
+// backward (Miller) values go through `lg`, this wave's LDS scratch
+// [NMB][64].  Ss points at the source's strengths of modes 0..NMB-1 for this
+// right-hand side (zero beyond nmodes).
+template <int NMB, int MODE>
+__device__ __forceinline__ void pair_accum(double r, double r1, double x, double inv_r, double inv_r1, bool use,
+                                           double chistar, int nmodes, const double2 *Ss,
+                                           Acc<NMB, MODE> &A, double *__restrict__ lg)
+{
+    const int lane = threadIdx.x & 63;
+    const double dr = r - r1, sr = r + r1;
+    double rm2 = fma(dr, dr, x * x);
+    const double rp2 = fma(sr, sr, x * x);
+    if (!use) rm2 = rp2;
+    const double inv_rr = inv_r * inv_r1;
+    PairStart ps = pair_start(rm2, rp2, r * r1, inv_rr);
+    if (!use) {
+        ps.g0 = 0.0;
+        ps.g1 = 0.0;
+        ps.chi = 1.0;
+    }
+    const bool back = (NMB > 2) && ps.chi >= chistar;
+    const bool anyback = __ballot(back) != 0;
+    double scale = 0.0;
+    if constexpr (NMB > 2) {
+        if (anyback) {
+            double dmin = wave_min(back ? ps.dchi : 1e300);
+            int extra = 10 + (int)ceil(20.0 * __builtin_amdgcn_rsq(2.0 * dmin));
+            // steps above the stored modes, a multiple of 8 (more steps only
+            // add accuracy); coefficients of 8 steps are fetched together
+            int nsteps = nmodes - 1 + extra - (NMB - 1);
+            nsteps = (nsteps + 7) & ~7;
+            if (nsteps < 8) nsteps = 8;
+            if (NMB - 1 + nsteps > kMillerMax) nsteps = (kMillerMax - NMB + 1) & ~7;
+            const int ntop = __builtin_amdgcn_readfirstlane(NMB - 1 + nsteps);
+            const double chi = ps.chi;
+            double yp = 0.0, y = 1.0;
+            for (int n = ntop; n >= NMB; n -= 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double ym = fma(c_down.a[n - u] * chi, y, -c_down.b[n - u] * yp);
+                    yp = y;
+                    y = ym;
+                }
+                if (fabs(y) > 0x1p500) {
+                    y *= 0x1p-500;
+                    yp *= 0x1p-500;
+                }
+            }
+            // keep the growth of the last NMB-1 steps in range
+            double lam = chi + fast_sqrt(ps.dchi * (chi + 1.0));
+            int e = ilogb(y) + (int)ceil((NMB - 1) * log2(lam)) - 16;
+            int emax = ilogb(y) + 1000;
+            if (e > emax) e = emax;
+            y = ldexp(y, -e);
+            yp = ldexp(yp, -e);
+            lg[(NMB - 1) * 64 + lane] = y;
+            double up = yp;
+#pragma unroll
+            for (int n = NMB - 1; n >= 1; --n) {
+                const double fa = 4.0 * n / (2.0 * n - 1.0), fb = (2.0 * n + 1.0) / (2.0 * n - 1.0);
+                double ym = fma(fa * chi, y, -fb * up);
+                up = y;
+                y = ym;
+                lg[(n - 1) * 64 + lane] = y;
+            }
+            scale = ps.g0 * fast_rcp(y);
+        }
+    }
+    // stream over modes
+    const double chi = ps.chi;
+    double gprev = ps.g1;       // G^(n-1), with G^(-1) = G^(1)
+    double gcur = ps.g0;        // forward value of G^(n)
+    double gnext = ps.g1;
+    double iprp = 0.0, iprm = 0.0, Ar = 0.0, hr = 0.0;
+    if constexpr (MODE != 0) {
+        iprp = fast_rcp(rp2);
+        iprm = fast_rcp(rm2);
+        Ar = (r * r - r1 * r1 - x * x) * 0.5 * inv_r;
+        hr = -0.5 * inv_r;
+        if (anyback && back) gprev = scale * lg[1 * 64 + lane];
+    }
+#pragma unroll
+    for (int n = 0; n < NMB; ++n) {
+        {
+            double g = gcur;
+            if constexpr (NMB > 2) {
+                if (anyback) g = back ? scale * lg[n * 64 + lane] : g;
+            }
+            const double2 v = Ss[n];
+            A.ar[n] = fma(g, v.x, A.ar[n]);
+            A.ai[n] = fma(g, v.y, A.ai[n]);
+            if constexpr (MODE != 0) {
+                const double nu = n - 0.5;
+                const double W = (g + gprev) * iprp + (g - gprev) * iprm;
+                const double gdr = fma(hr, g, nu * Ar * W);
+                const double gdx = nu * x * W;
+                A.rr_[n] = fma(gdr, v.x, A.rr_[n]);
+                A.ri_[n] = fma(gdr, v.y, A.ri_[n]);
+                A.zr_[n] = fma(gdx, v.x, A.zr_[n]);
+                A.zi_[n] = fma(gdx, v.y, A.zi_[n]);
+                gprev = g;
+            }
+            // bound the scheduling window: keeps only a few modes' loads in flight
+            if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            // forward recursion for the next mode
+            if (n + 1 < NMB) {
+                double gn;
+                if (n == 0) {
+                    gn = ps.g1;
+                } else {
+                    const double fa = 4.0 * n / (2.0 * n + 1.0), fb = (2.0 * n - 1.0) / (2.0 * n + 1.0);
+                    gn = fma(fa * chi, gcur, -fb * gnext);
+                }
+                gnext = gcur;   // holds G^(n) for the next step's G^(n-1)
+                gcur = gn;
+            }
+        }
+    }
+}
+
+// Deterministic sum of the four waves' accumulators through LDS; wave 0
+// ends with the totals.  buf: [64][NMB] doubles per component.
+template <int NMB, int MODE>
+__device__ __forceinline__ void reduce_waves(Acc<NMB, MODE> &A, double *__restrict__ buf, int nmodes)
+{
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    constexpr int K = MODE ? 6 : 2;
+    for (int src = 3; src >= 1; --src) {
+        __syncthreads();
+        if (w == src) {
+#pragma unroll
+            for (int n = 0; n < NMB; ++n) {
+                if (n < nmodes) {
+                    double *b = buf + ((size_t)n * 64 + lane) * K;
+                    double v[6] = {A.ar[n], A.ai[n], 0, 0, 0, 0};
+                    if constexpr (MODE != 0) {
+                        v[2] = A.rr_[n]; v[3] = A.ri_[n]; v[4] = A.zr_[n]; v[5] = A.zi_[n];
+                    }
+                    if (src == 3) {
+                        for (int k = 0; k < K; ++k) b[k] = v[k];
+                    } else {
+                        for (int k = 0; k < K; ++k) b[k] += v[k];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int n = 0; n < NMB; ++n) {
+            if (n < nmodes) {
+                const double *b = buf + ((size_t)n * 64 + lane) * K;
+                A.ar[n] += b[0];
+                A.ai[n] += b[1];
+                if constexpr (MODE != 0) {
+                    A.rr_[n] += b[2]; A.ri_[n] += b[3]; A.zr_[n] += b[4]; A.zi_[n] += b[5];
+                }
+            }
+        }
+    }
+}
+
+template <int NMB, int MODE>
+constexpr size_t leaf_lds_doubles()
+{
+    size_t miller = (size_t)4 * NMB * 64;
+    size_t red = (size_t)64 * NMB * (MODE ? 6 : 2);
+    return miller > red ? miller : red;
+}
+
+// scratch + staged source tile (64 sources: strengths, r, z, 1/r)
+template <int NMB, int MODE>
+constexpr size_t leaf_lds_bytes()
+{
+    return leaf_lds_doubles<NMB, MODE>() * sizeof(double) + (size_t)64 * NMB * 16 + 3 * 64 * sizeof(double);
+}
+
 // ------------------------------------------------------------ leaf pass
-// One wave per chunk of <= 64 targets of one leaf: local expansion
-// (eq. analysis:local) plus the direct sum over the 3x3 neighbour leaves.
+// One block (four waves) per chunk of <= 64 targets of one leaf: local
+// expansion (eq. analysis:local) plus the direct sum over the 3x3 neighbour
+// leaves, the sources dealt round-robin to the four waves.
 // MODE 0: potential; 1: potential and gradient; 2: potential and the
 // adjoint coordinate contraction.
 template <int NMB, int MODE>
-__global__ __launch_bounds__(64) void k_leaf(int M, int nmodes, int nrhs, int depth, double rlo, double zlo,
-                                            double invh, double chistar, const int4 *__restrict__ chunks,
-                                            SideView tv, SideView sv, const double2 *__restrict__ Sg,
-                                            const double2 *__restrict__ loc, double2 *__restrict__ phi,
-                                            double2 *__restrict__ dphr, double2 *__restrict__ dphz,
-                                            const double2 *__restrict__ Sdot, double *__restrict__ gr,
-                                            double *__restrict__ gz, int64_t ntot)
+__global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int depth, double rlo, double zlo,
+                                             double invh, double chistar, const int4 *__restrict__ chunks,
+                                             SideView tv, SideView sv, const double *__restrict__ sinv,
+                                             const double2 *__restrict__ Sg, const double2 *__restrict__ loc,
+                                             double2 *__restrict__ phi, double2 *__restrict__ dphr,
+                                             double2 *__restrict__ dphz, const double2 *__restrict__ Sdot,
+                                             double *__restrict__ gr, double *__restrict__ gz, int64_t ntot,
+                                             int Cs)
 {
+    extern __shared__ double lds[];
+    double2 *st_S = reinterpret_cast<double2 *>(lds + leaf_lds_doubles<NMB, MODE>());
+    double *st_r = reinterpret_cast<double *>(st_S + 64 * NMB);
+    double *st_z = st_r + 64, *st_i = st_z + 64;
     const int4 ch = chunks[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const bool active = lane < ch.z;
     const int t = ch.y + (active ? lane : 0);
     const int nb = 1 << depth;
@@ -348,39 +749,38 @@ __global__ __launch_bounds__(64) void k_leaf(int M, int nmodes, int nrhs, int de
     const double r = tv.r[t], z = tv.z[t];
     const double xr = (r - rlo) * invh - (ir + 0.5);
     const double xz = (z - zlo) * invh - (iz + 0.5);
-    const double inv_r = 1.0 / r;
+    const double inv_r = fast_rcp(r);
     const int orig = tv.perm[t];
+    double *lg = lds + (size_t)w * NMB * 64;
     double gsr = 0.0, gsz = 0.0;
     for (int q = 0; q < nrhs; ++q) {
-        double ar[NMB], ai[NMB];
-        double drr[MODE ? NMB : 1], dri[MODE ? NMB : 1], dzr[MODE ? NMB : 1], dzi[MODE ? NMB : 1];
-#pragma unroll
-        for (int n = 0; n < NMB; ++n) {
-            ar[n] = ai[n] = 0.0;
-            if constexpr (MODE != 0) drr[n] = dri[n] = dzr[n] = dzi[n] = 0.0;
-        }
-        // local expansion
+        Acc<NMB, MODE> A;
+        A.zero();
+        // local expansion, monomials dealt round-robin over the waves
         const double2 *lc = loc + (int64_t)ch.x * C * P;
         {
-            double pr = 1.0, pr1 = 0.0;   // xr^k, k xr^(k-1)
+            double pr = 1.0, pr1 = 0.0;
             int p = 0;
             for (int kk = 0; kk <= M; ++kk) {
                 double pz = 1.0, pz1 = 0.0;
                 for (int ll = 0; kk + ll <= M; ++ll, ++p) {
-                    double w = pr * pz;
+                    if ((p & 3) == w) {
+                        const double wv = pr * pz;
 #pragma unroll
-                    for (int n = 0; n < NMB; ++n) {
-                        if (n < nmodes) {
-                            double2 v = lc[(int64_t)(n * nrhs + q) * P + p];
-                            ar[n] += w * v.x;
-                            ai[n] += w * v.y;
-                            if constexpr (MODE != 0) {
-                                double wr = pr1 * pz * invh, wz = pr * pz1 * invh;
-                                drr[n] += wr * v.x;
-                                dri[n] += wr * v.y;
-                                dzr[n] += wz * v.x;
-                                dzi[n] += wz * v.y;
+                        for (int n = 0; n < NMB; ++n) {
+                            if (n < nmodes) {
+                                const double2 v = lc[(int64_t)(n * nrhs + q) * P + p];
+                                A.ar[n] = fma(wv, v.x, A.ar[n]);
+                                A.ai[n] = fma(wv, v.y, A.ai[n]);
+                                if constexpr (MODE != 0) {
+                                    const double wr = pr1 * pz * invh, wz = pr * pz1 * invh;
+                                    A.rr_[n] = fma(wr, v.x, A.rr_[n]);
+                                    A.ri_[n] = fma(wr, v.y, A.ri_[n]);
+                                    A.zr_[n] = fma(wz, v.x, A.zr_[n]);
+                                    A.zi_[n] = fma(wz, v.y, A.zi_[n]);
+                                }
                             }
+                            if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);
                         }
                     }
                     pz1 = (ll + 1) * pz;
@@ -390,80 +790,65 @@ __global__ __launch_bounds__(64) void k_leaf(int M, int nmodes, int nrhs, int de
                 pr *= xr;
             }
         }
-        // near field
-        for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr) {
+        // near field: the sources of the 3x3 neighbour leaves in tiles of 64,
+        // staged in LDS, dealt round-robin to the four waves
+        int rb[9], re[9], nr = 0, total = 0;
+        for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
             for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) {
                 const uint32_t m = morton((uint32_t)jr, (uint32_t)jz);
-                const int s0 = sv.off[m], s1 = sv.off[m + 1];
-                for (int s = s0; s < s1; ++s) {
-                    const double r1 = sv.r[s], z1 = sv.z[s];
-                    const double dr = r - r1, x = z - z1, sr = r + r1;
-                    double rm2 = dr * dr + x * x;
-                    const double rp2 = sr * sr + x * x;
-                    const bool use = active && rm2 != 0.0;
-                    if (!use) rm2 = rp2 > 0.0 ? rp2 : 1.0;
-                    const double rr = r * r1, inv_rr = inv_r / r1;
-                    double G[NMB];
-                    green_modes<NMB>(rm2, rp2, rr, inv_rr, chistar, nmodes, G);
-                    const double2 *Ss = Sg + (int64_t)s * C + q;
-                    const double wgt = use ? 1.0 : 0.0;
-                    if constexpr (MODE == 0) {
-#pragma unroll
-                        for (int n = 0; n < NMB; ++n) {
-                            if (n < nmodes) {
-                                double2 v = Ss[n * nrhs];
-                                double g = G[n] * wgt;
-                                ar[n] += g * v.x;
-                                ai[n] += g * v.y;
-                            }
-                        }
-                    } else {
-                        const double iprp = 1.0 / rp2, iprm = 1.0 / rm2;
-                        const double A = (r * r - r1 * r1 - x * x) * 0.5 * inv_r;
-                        const double hr = -0.5 * inv_r;
-#pragma unroll
-                        for (int n = 0; n < NMB; ++n) {
-                            if (n < nmodes) {
-                                double2 v = Ss[n * nrhs];
-                                double gn = G[n], gm = G[n == 0 ? (NMB > 1 ? 1 : 0) : n - 1];
-                                double W = (gn + gm) * iprp + (gn - gm) * iprm;
-                                double nu = n - 0.5;
-                                double gdr = (hr * gn + nu * A * W) * wgt;
-                                double gdx = nu * x * W * wgt;
-                                double g = gn * wgt;
-                                ar[n] += g * v.x;
-                                ai[n] += g * v.y;
-                                drr[n] += gdr * v.x;
-                                dri[n] += gdr * v.y;
-                                dzr[n] += gdx * v.x;
-                                dzi[n] += gdx * v.y;
-                            }
-                        }
-                    }
+                rb[nr] = sv.off[m];
+                re[nr] = sv.off[m + 1];
+                total += re[nr] - rb[nr];
+                ++nr;
+            }
+        for (int tile = 0; tile < total; tile += 64) {
+            __syncthreads();
+            const int cnt = min(64, total - tile);
+            for (int e = threadIdx.x; e < cnt * NMB; e += 256) {
+                const int k = e / NMB, n = e - k * NMB;
+                int li = tile + k, rr = 0;
+                while (li >= re[rr] - rb[rr]) {
+                    li -= re[rr] - rb[rr];
+                    ++rr;
+                }
+                const int s = rb[rr] + li;
+                st_S[k * NMB + n] = Sg[(int64_t)s * Cs + n * nrhs + q];
+                if (n == 0) {
+                    st_r[k] = sv.r[s];
+                    st_z[k] = sv.z[s];
+                    st_i[k] = sinv[s];
                 }
             }
+            __syncthreads();
+            for (int k = w; k < cnt; k += 4) {
+                const double r1 = st_r[k], x = z - st_z[k];
+                const bool use = active && !(r == r1 && x == 0.0);
+                pair_accum<NMB, MODE>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, st_S + k * NMB, A, lg);
+            }
         }
-        if (active) {
+        reduce_waves<NMB, MODE>(A, lds, nmodes);
+        if (w == 0 && active) {
 #pragma unroll
             for (int n = 0; n < NMB; ++n) {
                 if (n < nmodes) {
                     int64_t o = ((int64_t)q * nmodes + n) * ntot + orig;
-                    phi[o] = make_double2(ar[n], ai[n]);
+                    phi[o] = make_double2(A.ar[n], A.ai[n]);
                     if constexpr (MODE == 1) {
-                        if (dphr) dphr[o] = make_double2(drr[n], dri[n]);
-                        if (dphz) dphz[o] = make_double2(dzr[n], dzi[n]);
+                        if (dphr) dphr[o] = make_double2(A.rr_[n], A.ri_[n]);
+                        if (dphz) dphz[o] = make_double2(A.zr_[n], A.zi_[n]);
                     }
                     if constexpr (MODE == 2) {
-                        double2 s = Sdot[o];
-                        gsr += s.x * drr[n] + s.y * dri[n];
-                        gsz += s.x * dzr[n] + s.y * dzi[n];
+                        double2 sd = Sdot[o];
+                        gsr += sd.x * A.rr_[n] + sd.y * A.ri_[n];
+                        gsz += sd.x * A.zr_[n] + sd.y * A.zi_[n];
                     }
                 }
             }
         }
+        __syncthreads();
     }
     if constexpr (MODE == 2) {
-        if (active) {
+        if (w == 0 && active) {
             if (gr) gr[orig] = gsr;
             if (gz) gz[orig] = gsz;
         }
@@ -471,48 +856,55 @@ __global__ __launch_bounds__(64) void k_leaf(int M, int nmodes, int nrhs, int de
 }
 
 // ---------------------------------------------------------------- direct
+// One block (four waves) per 64 targets; each wave takes every fourth source.
 template <int NMB>
 __global__ __launch_bounds__(256) void k_direct(int nmodes, int nrhs, double chistar, SideView tv, int64_t nt,
-                                               SideView sv, int64_t ns, const double2 *__restrict__ Sg,
-                                               double2 *__restrict__ phi)
+                                               SideView sv, const double *__restrict__ sinv, int64_t ns,
+                                               const double2 *__restrict__ Sg, double2 *__restrict__ phi, int Cs)
 {
-    const int64_t tg = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    extern __shared__ double lds[];
+    double2 *st_S = reinterpret_cast<double2 *>(lds + leaf_lds_doubles<NMB, 0>());
+    double *st_r = reinterpret_cast<double *>(st_S + 64 * NMB);
+    double *st_z = st_r + 64, *st_i = st_z + 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t tg = blockIdx.x * (int64_t)64 + lane;
     const bool active = tg < nt;
     const int64_t t = active ? tg : 0;
     const int C = nmodes * nrhs;
     const double r = tv.r[t], z = tv.z[t];
-    const double inv_r = 1.0 / r;
+    const double inv_r = fast_rcp(r);
+    double *lg = lds + (size_t)w * NMB * 64;
     for (int q = 0; q < nrhs; ++q) {
-        double ar[NMB], ai[NMB];
-#pragma unroll
-        for (int n = 0; n < NMB; ++n) ar[n] = ai[n] = 0.0;
-        for (int64_t s = 0; s < ns; ++s) {
-            const double r1 = sv.r[s], z1 = sv.z[s];
-            const double dr = r - r1, x = z - z1, sr = r + r1;
-            double rm2 = dr * dr + x * x;
-            const double rp2 = sr * sr + x * x;
-            const bool use = rm2 != 0.0;
-            if (!use) rm2 = rp2;
-            double G[NMB];
-            green_modes<NMB>(rm2, rp2, r * r1, inv_r / r1, chistar, nmodes, G);
-            const double2 *Ss = Sg + s * C + q;
-            const double wgt = use ? 1.0 : 0.0;
-#pragma unroll
-            for (int n = 0; n < NMB; ++n) {
-                if (n < nmodes) {
-                    double2 v = Ss[n * nrhs];
-                    double g = G[n] * wgt;
-                    ar[n] += g * v.x;
-                    ai[n] += g * v.y;
+        Acc<NMB, 0> A;
+        A.zero();
+        for (int64_t tile = 0; tile < ns; tile += 64) {
+            __syncthreads();
+            const int cnt = (int)min((int64_t)64, ns - tile);
+            for (int e = threadIdx.x; e < cnt * NMB; e += 256) {
+                const int k = e / NMB, n = e - k * NMB;
+                const int64_t s = tile + k;
+                st_S[k * NMB + n] = Sg[s * Cs + n * nrhs + q];
+                if (n == 0) {
+                    st_r[k] = sv.r[s];
+                    st_z[k] = sv.z[s];
+                    st_i[k] = sinv[s];
                 }
             }
+            __syncthreads();
+            for (int k = w; k < cnt; k += 4) {
+                const double r1 = st_r[k], x = z - st_z[k];
+                const bool use = active && !(r == r1 && x == 0.0);
+                pair_accum<NMB, 0>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, st_S + k * NMB, A, lg);
+            }
         }
-        if (active) {
+        reduce_waves<NMB, 0>(A, lds, nmodes);
+        if (w == 0 && active) {
             const int orig = tv.perm[t];
 #pragma unroll
             for (int n = 0; n < NMB; ++n)
-                if (n < nmodes) phi[((int64_t)q * nmodes + n) * nt + orig] = make_double2(ar[n], ai[n]);
+                if (n < nmodes) phi[((int64_t)q * nmodes + n) * nt + orig] = make_double2(A.ar[n], A.ai[n]);
         }
+        __syncthreads();
     }
 }
 
@@ -526,38 +918,76 @@ SideView view_of(const Side &s)
     return v;
 }
 
-template <int NMB>
-void launch_leaf(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
+template <int LB, int TB>
+void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
+{
+    size_t shm = sizeof(double2) * (size_t)TB * pl.P;
+    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C, 64, shm, st>>>(
+        pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l],
+        l > 2 ? tgt.slot[l - 1] : nullptr, l > 2 ? pl.lev[l - 1].loc : nullptr, src.slot[l], pl.lev[l].mom,
+        pl.lev[l].tab, pl.lev[l].loc);
+}
+
+void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
+{
+    switch (s2l_lb(pl.M)) {
+    case 1: launch_s2l_t<1, 8>(pl, src, tgt, l, st); break;
+    case 2: launch_s2l_t<2, 8>(pl, src, tgt, l, st); break;
+    case 3: launch_s2l_t<3, 8>(pl, src, tgt, l, st); break;
+    case 4: launch_s2l_t<4, 4>(pl, src, tgt, l, st); break;
+    case 5: launch_s2l_t<5, 4>(pl, src, tgt, l, st); break;
+    case 6: launch_s2l_t<6, 4>(pl, src, tgt, l, st); break;
+    case 7: launch_s2l_t<7, 4>(pl, src, tgt, l, st); break;
+    default: launch_s2l_t<8, 4>(pl, src, tgt, l, st); break;
+    }
+}
+
+template <int NMB, int MODE>
+void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
 {
     SideView tv = view_of(tgt), sv = view_of(src);
     double invh = (double)(1 << pl.d) * pl.invL;
     const double2 *loc = pl.lev[pl.d].loc;
-    dim3 g(tgt.nchunks);
-    auto *phi = (double2 *)out.phi;
-    if (out.mode == 0)
-        k_leaf<NMB, 0><<<g, 64, 0, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh, pl.chistar,
-                                         tgt.chunks, tv, sv, pl.Sg, loc, phi, nullptr, nullptr, nullptr,
-                                         nullptr, nullptr, tgt.n);
-    else if (out.mode == 1)
-        k_leaf<NMB, 1><<<g, 64, 0, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh, pl.chistar,
-                                         tgt.chunks, tv, sv, pl.Sg, loc, phi, (double2 *)out.dr,
-                                         (double2 *)out.dz, nullptr, nullptr, nullptr, tgt.n);
-    else
-        k_leaf<NMB, 2><<<g, 64, 0, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh, pl.chistar,
-                                         tgt.chunks, tv, sv, pl.Sg, loc, phi, nullptr, nullptr,
-                                         (const double2 *)out.Sdot, out.gr, out.gz, tgt.n);
+    constexpr size_t shm = leaf_lds_bytes<NMB, MODE>();
+    static bool attr[64] = {};
+    if (shm > 65536 && !attr[pl.device & 63]) {
+        AXF_HIP(hipFuncSetAttribute((const void *)k_leaf<NMB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+        attr[pl.device & 63] = true;
+    }
+    if (tgt.nchunks == 0) return;
+    k_leaf<NMB, MODE><<<tgt.nchunks, 256, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
+                                                     pl.chistar, tgt.chunks, tv, sv, src.rinv, pl.Sg, loc,
+                                                     (double2 *)out.phi, (double2 *)out.dr, (double2 *)out.dz,
+                                                     (const double2 *)out.Sdot, out.gr, out.gz, tgt.n,
+                                                     NMB * pl.nrhs);
+}
+
+template <int NMB>
+void launch_leaf(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
+{
+    if (out.mode == 0) launch_leaf_mode<NMB, 0>(pl, src, tgt, out, st);
+    else if (out.mode == 1) launch_leaf_mode<NMB, 1>(pl, src, tgt, out, st);
+    else launch_leaf_mode<NMB, 2>(pl, src, tgt, out, st);
 }
 
 template <int NMB>
 void launch_direct(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
 {
     SideView tv = view_of(tgt), sv = view_of(src);
-    int g = (int)((tgt.n + 255) / 256);
-    k_direct<NMB><<<g, 256, 0, st>>>(pl.nmodes, pl.nrhs, pl.chistar, tv, tgt.n, sv, src.n, pl.Sg,
-                                      (double2 *)out.phi);
+    int g = (int)((tgt.n + 63) / 64);
+    constexpr size_t shm = leaf_lds_bytes<NMB, 0>();
+    static bool attr[64] = {};
+    if (shm > 65536 && !attr[pl.device & 63]) {
+        AXF_HIP(hipFuncSetAttribute((const void *)k_direct<NMB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+        attr[pl.device & 63] = true;
+    }
+    k_direct<NMB><<<g, 256, shm, st>>>(pl.nmodes, pl.nrhs, pl.chistar, tv, tgt.n, sv, src.rinv, src.n, pl.Sg,
+                                       (double2 *)out.phi, NMB * pl.nrhs);
 }
 
-#define AXF_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(64)
+#define AXF_BUCKETS(X) X(4) X(9) X(12) X(17) X(24) X(33) X(48) X(64)
 
 }  // namespace
 
@@ -566,29 +996,35 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
     const int M = pl.M, P = pl.P, C = pl.C, d = pl.d;
     const int64_t ns = src.n;
     {
-        int64_t tot = ns * C;
+        PhaseTimer tm(pl, st, AXF_PHASE_GATHER);
+        int64_t tot = ns * pl.Cs;
         k_gather<<<(int)((tot + 255) / 256), 256, 0, st>>>((const double2 *)S, src.perm, ns, pl.nmodes, pl.nrhs,
-                                                          pl.Sg);
+                                                          pl.Cs, pl.Sg);
     }
     SideView sv = view_of(src);
-    if (src.nocc[d] > 0)
-        k_p2m<<<src.nocc[d], 256, 0, st>>>(M, C, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
+    if (src.nocc[d] > 0) {
+        PhaseTimer tm(pl, st, AXF_PHASE_P2M);
+        k_p2m<<<src.nocc[d], 256, 0, st>>>(M, C, pl.Cs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
                                            pl.Sg, pl.lev[d].mom);
-    for (int l = d - 1; l >= 2; --l)
-        if (src.nocc[l] > 0)
-            k_m2m<<<src.nocc[l], 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
-                                               pl.lev[l].mom);
-    for (int l = 2; l <= d; ++l) {
-        if (tgt.nocc[l] == 0) continue;
-        size_t shm = sizeof(double2) * (size_t)pl.nrhs * P;
-        k_s2l<<<tgt.nocc[l] * pl.nmodes, 256, shm, st>>>(M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.box[l],
-                                                         l > 2 ? tgt.slot[l - 1] : nullptr,
-                                                         l > 2 ? pl.lev[l - 1].loc : nullptr, src.slot[l],
-                                                         pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc);
     }
-    const int nm = pl.nmodes;
+    {
+        PhaseTimer tm(pl, st, AXF_PHASE_M2M);
+        for (int l = d - 1; l >= 2; --l)
+            if (src.nocc[l] > 0)
+                k_m2m<<<src.nocc[l], 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
+                                                   pl.lev[l].mom);
+    }
+    {
+        PhaseTimer tm_s2l(pl, st, AXF_PHASE_S2L);
+        for (int l = 2; l <= d; ++l) {
+            if (tgt.ntiles[l] == 0) continue;
+            launch_s2l(pl, src, tgt, l, st);
+        }
+    }
+    (void)pl.nmodes;
+    PhaseTimer tm_leaf(pl, st, AXF_PHASE_LEAF);
 #define AXF_LEAF(B)                                         \
-    if (nm <= B) {                                          \
+    if (pl.nmb == B) {                                      \
         launch_leaf<B>(pl, src, tgt, out, st);              \
         AXF_HIP(hipGetLastError());                         \
         return;                                             \
@@ -601,11 +1037,16 @@ void run_direct(Plan &pl, const Side &src, const Side &tgt, const double *S, con
 {
     const int64_t ns = src.n;
     const int C = pl.C;
-    int64_t tot = ns * C;
-    k_gather<<<(int)((tot + 255) / 256), 256, 0, st>>>((const double2 *)S, src.perm, ns, pl.nmodes, pl.nrhs, pl.Sg);
-    const int nm = pl.nmodes;
+    int64_t tot = ns * pl.Cs;
+    {
+        PhaseTimer tm(pl, st, AXF_PHASE_GATHER);
+        k_gather<<<(int)((tot + 255) / 256), 256, 0, st>>>((const double2 *)S, src.perm, ns, pl.nmodes, pl.nrhs,
+                                                          pl.Cs, pl.Sg);
+    }
+    (void)pl.nmodes;
+    PhaseTimer tm_dir(pl, st, AXF_PHASE_DIRECT);
 #define AXF_DIR(B)                                          \
-    if (nm <= B) {                                          \
+    if (pl.nmb == B) {                                      \
         launch_direct<B>(pl, src, tgt, out, st);            \
         AXF_HIP(hipGetLastError());                         \
         return;                                             \

@@ -76,6 +76,7 @@ struct Sizer {
 struct Side {
     int64_t n = 0;
     double *r = nullptr, *z = nullptr;      // sorted coordinates [n]
+    double *rinv = nullptr;                 // 1 / r, sorted [n]
     int32_t *perm = nullptr;                // sorted position -> caller index
     int32_t *off = nullptr;                 // leaf offsets in Morton order [4^d + 1]
     int32_t *slot[AXF_MAX_DEPTH + 1] = {};  // [4^l]: box id -> compact slot, -1 if empty
@@ -84,7 +85,24 @@ struct Side {
     int4 *chunks = nullptr;                 // leaf work: (slot, first, count, box)
     int nchunks = 0;
     int max_leaf = 0;
+    // S2L tiles of this side as targets: (station, z parity, first, count)
+    int4 *tiles[AXF_MAX_DEPTH + 1] = {};
+    int32_t *tile_slots[AXF_MAX_DEPTH + 1] = {};
+    int ntiles[AXF_MAX_DEPTH + 1] = {};
 };
+
+// Output-block width of the tiled S2L (smallest that fits the outputs of
+// one mode in a 64-lane wave) and boxes per tile.
+inline int s2l_lb(int M)
+{
+    for (int lb = 1; lb <= 8; ++lb) {
+        int s = 0;
+        for (int k = 0; k <= M; ++k) s += (M + 1 - k + lb - 1) / lb;
+        if (s <= 64) return lb;
+    }
+    return 8;
+}
+inline int s2l_tb(int M) { return s2l_lb(M) <= 3 ? 8 : 4; }
 
 struct Level {
     int nb = 0;                // boxes per side, 2^l
@@ -94,26 +112,57 @@ struct Level {
     double *tab = nullptr;     // [nb][12][n_modes][TS] S2L tables (x >= 0, outer >= inner)
 };
 
+// Mode counts the near-field kernels are compiled for; a plan uses the
+// smallest one >= n_modes and pads the strengths with zeros.
+inline int mode_bucket(int nmodes)
+{
+    const int b[] = {4, 9, 12, 17, 24, 33, 48, 64};
+    for (int v : b)
+        if (nmodes <= v) return v;
+    return 64;
+}
+
 struct Plan {
     int device = 0;
     axf_params p{};
     int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
+    int nmb = 4, Cs = 4;        // mode bucket and padded channels per point in Sg
     double rlo = 0, zlo = 0, L = 1, invL = 1;
     double chistar = 1e300;
     Side src, fld;
     Level lev[AXF_MAX_DEPTH + 1];
-    double2 *Sg = nullptr;      // gathered strengths, point-major [max(ns, nf)][C]
+    double2 *Sg = nullptr;      // gathered strengths, point-major [max(ns, nf)][Cs]
     double *gsum = nullptr;     // adjoint coordinate-gradient scratch
     double *tab_scratch = nullptr;
-    Arena points, tree, expn;
+    Arena points, tree, expn, tilemem;
     int64_t near_pairs = 0, s2l_pairs = 0;
     size_t device_bytes = 0;
+    // phase timing (HIP events on the evaluation stream)
+    bool timing = false;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare_events;
+};
+
+// Records HIP events around a pass when the plan's timing is enabled.
+struct PhaseTimer {
+    Plan &pl;
+    hipStream_t st;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(Plan &p, hipStream_t s, int ph);
+    ~PhaseTimer();
 };
 
 // -------------------------------------------------------------- launchers
+hipEvent_t event_get(Plan &pl);
 // tree (axf_tree.hip)
 void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, const double *zf,
                 hipStream_t st);
+void build_tiles(Plan &pl, hipStream_t st);
 // tables (axf_tables.hip)
 void build_tables(Plan &pl, hipStream_t st);
 size_t table_scratch_doubles(int d, int M, int nmodes);

@@ -3,6 +3,7 @@
 // point sets, leaf offsets, occupied-box slots per level and leaf work chunks.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "axf_device.hpp"
 #include "axf_internal.hpp"
@@ -227,13 +228,14 @@ __global__ void k_rs_scatter(const uint32_t *__restrict__ key, const int32_t *__
 // ----------------------------------------------------------- structure
 __global__ void k_gather_coords(const double *__restrict__ r, const double *__restrict__ z,
                                 const int32_t *__restrict__ perm, int64_t n, double *__restrict__ ro,
-                                double *__restrict__ zo)
+                                double *__restrict__ zo, double *__restrict__ rinv)
 {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t i = perm[p];
     ro[p] = r[i];
     zo[p] = z[i];
+    rinv[p] = 1.0 / r[i];
 }
 
 // off[m] = first sorted position with key >= m, m = 0..nleaf
@@ -306,6 +308,42 @@ __global__ void k_chunk_fill(const int32_t *__restrict__ off, const int32_t *__r
     for (int j = 0; j * 64 < cnt; ++j)
         chunks[c0 + j] = make_int4(k, first + j * 64, min(64, cnt - j * 64), b);
     if (k == nocc - 1) *total = c0 + (cnt + 63) / 64;
+}
+
+// Work counts: near-field pairs (targets x sources of the 3x3 neighbour
+// leaves) and S2L box pairs (occupied source boxes in each occupied target
+// box's interaction list).
+__global__ void k_count_near(const int32_t *__restrict__ toff, const int32_t *__restrict__ soff,
+                             const int32_t *__restrict__ tbox, int nocc, int depth,
+                             unsigned long long *__restrict__ out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nocc) return;
+    int nb = 1 << depth;
+    int b = tbox[k];
+    int ir = b / nb, iz = b - ir * nb;
+    long long nt = box_count(toff, depth, depth, b), ns = 0;
+    for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
+        for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) ns += box_count(soff, depth, depth, jr * nb + jz);
+    atomicAdd(out, (unsigned long long)(nt * ns));
+}
+
+__global__ void k_count_s2l(const int32_t *__restrict__ tbox, int nocc, const int32_t *__restrict__ sslot,
+                            int level, unsigned long long *__restrict__ out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nocc) return;
+    int nb = 1 << level;
+    int b = tbox[k];
+    int ir = b / nb, iz = b - ir * nb;
+    int c = 0;
+    for (int jr = 2 * (ir >> 1) - 2; jr < 2 * (ir >> 1) + 4; ++jr)
+        for (int jz = 2 * (iz >> 1) - 2; jz < 2 * (iz >> 1) + 4; ++jz) {
+            if (jr < 0 || jz < 0 || jr >= nb || jz >= nb) continue;
+            if (abs(jr - ir) <= 1 && abs(jz - iz) <= 1) continue;
+            if (sslot[jr * nb + jz] >= 0) ++c;
+        }
+    atomicAdd(out, (unsigned long long)c);
 }
 
 inline int nblk(int64_t n, int b = kBlk) { return (int)((n + b - 1) / b); }
@@ -383,9 +421,10 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     for (int64_t n : {ns, nf}) {
         sz.add<double>(n);
         sz.add<double>(n);
+        sz.add<double>(n);
         sz.add<int32_t>(n);
     }
-    sz.add<double2>((size_t)nmax * pl.C);      // gathered strengths
+    sz.add<double2>((size_t)nmax * pl.Cs);     // gathered strengths
     sz.add<double>(2 * (size_t)ns);            // adjoint coordinate-gradient scratch
     const int64_t nb11 = autod ? ((int64_t)1 << (2 * AXF_MAX_DEPTH)) : 0;
     if (autod) {
@@ -403,16 +442,19 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     int64_t tmp_ints = std::max<int64_t>(scan_tmp_ints(cnt_ints), scan_tmp_ints((int64_t)1 << (2 * AXF_MAX_DEPTH)));
     sz.add<int32_t>(tmp_ints);
     sz.add<int32_t>(64);
+    sz.add<unsigned long long>(4);
     pl.points = arena_acquire(sz.bytes + 4096);
     Arena &A = pl.points;
     double *bb = A.take<double>(5 * 1024 + 8);
     pl.src.r = A.take<double>(ns);
     pl.src.z = A.take<double>(ns);
+    pl.src.rinv = A.take<double>(ns);
     pl.src.perm = A.take<int32_t>(ns);
     pl.fld.r = A.take<double>(nf);
     pl.fld.z = A.take<double>(nf);
+    pl.fld.rinv = A.take<double>(nf);
     pl.fld.perm = A.take<int32_t>(nf);
-    pl.Sg = A.take<double2>((size_t)nmax * pl.C);
+    pl.Sg = A.take<double2>((size_t)nmax * pl.Cs);
     pl.gsum = A.take<double>(2 * (size_t)ns);
     uint32_t *k11s = nullptr, *k11f = nullptr;
     int32_t *hs = nullptr, *hf = nullptr;
@@ -430,6 +472,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     sb.counts = A.take<int32_t>(cnt_ints);
     sb.tmp = A.take<int32_t>(tmp_ints);
     int32_t *small = A.take<int32_t>(64);
+    unsigned long long *cnt64 = A.take<unsigned long long>(4);
 
     // ---- bounding square and validation
     int nbb = std::min<int64_t>(1024, std::max<int64_t>(1, (ns + nf + kBlk - 1) / kBlk));
@@ -520,7 +563,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
         k_keys<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, n, pl.rlo, pl.zlo, pl.invL, d, sb.k0, sb.v0);
         radix_sort(sb, n, bits, st);
         AXF_HIP(hipMemcpyAsync(s.perm, sb.v0, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-        k_gather_coords<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, s.perm, n, s.r, s.z);
+        k_gather_coords<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, s.perm, n, s.r, s.z, s.rinv);
         k_offsets<<<nblk(nleaf + 1), kBlk, 0, st>>>(sb.k0, n, nleaf, s.off);
         for (int l = 2; l <= d; ++l) {
             int nbox = 1 << (2 * l);
@@ -541,12 +584,86 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
         scan_excl(flag, pre, nocc, sb.tmp, st);
         k_chunk_fill<<<nblk(nocc), kBlk, 0, st>>>(s.off, s.box[d], nocc, d, pre, s.chunks, small + 2 + side);
     }
+    AXF_HIP(hipMemsetAsync(cnt64, 0, 4 * sizeof(unsigned long long), st));
+    k_count_near<<<nblk(pl.fld.nocc[d]), kBlk, 0, st>>>(pl.fld.off, pl.src.off, pl.fld.box[d], pl.fld.nocc[d], d,
+                                                        cnt64);
+    for (int l = 2; l <= d; ++l)
+        k_count_s2l<<<nblk(pl.fld.nocc[l]), kBlk, 0, st>>>(pl.fld.box[l], pl.fld.nocc[l], pl.src.slot[l], l,
+                                                           cnt64 + 1);
+    unsigned long long h_cnt[4];
     AXF_HIP(hipMemcpyAsync(h_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipMemcpyAsync(h_cnt, cnt64, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipStreamSynchronize(st));
+    pl.near_pairs = (int64_t)h_cnt[0];
+    pl.s2l_pairs = (int64_t)h_cnt[1];
     pl.src.max_leaf = h_small[0];
     pl.fld.max_leaf = h_small[1];
     pl.src.nchunks = h_small[2];
     pl.fld.nchunks = h_small[3];
+}
+
+// S2L tiles: occupied target boxes grouped by (station, z parity), TB per
+// tile, for both sides (the adjoint uses the sources as targets).
+void build_tiles(Plan &pl, hipStream_t st)
+{
+    const int TB = s2l_tb(pl.M);
+    Side *sides[2] = {&pl.src, &pl.fld};
+    std::vector<int32_t> hb;
+    std::vector<std::vector<int4>> tiles(2 * (AXF_MAX_DEPTH + 1));
+    std::vector<std::vector<int32_t>> slots(2 * (AXF_MAX_DEPTH + 1));
+    size_t bytes = 0;
+    for (int si = 0; si < 2; ++si) {
+        Side &s = *sides[si];
+        for (int l = 2; l <= pl.d; ++l) {
+            int n = s.nocc[l];
+            hb.resize(n);
+            if (n) AXF_HIP(hipMemcpyAsync(hb.data(), s.box[l], n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            AXF_HIP(hipStreamSynchronize(st));
+            const int nb = 1 << l;
+            auto &tv = tiles[si * (AXF_MAX_DEPTH + 1) + l];
+            auto &sv = slots[si * (AXF_MAX_DEPTH + 1) + l];
+            // boxes are station-major in slot order; split each station by parity
+            int k = 0;
+            while (k < n) {
+                int station = hb[k] / nb, e = k;
+                while (e < n && hb[e] / nb == station) ++e;
+                for (int par = 0; par < 2; ++par) {
+                    int first = (int)sv.size();
+                    for (int j = k; j < e; ++j)
+                        if (((hb[j] - station * nb) & 1) == par) sv.push_back(j);
+                    for (int f = first; f < (int)sv.size(); f += TB)
+                        tv.push_back(make_int4(station, par, f, std::min(TB, (int)sv.size() - f)));
+                }
+                k = e;
+            }
+            bytes += tv.size() * sizeof(int4) + sv.size() * sizeof(int32_t) + 512;
+        }
+    }
+    Sizer sz;
+    for (int si = 0; si < 2; ++si)
+        for (int l = 2; l <= pl.d; ++l) {
+            sz.add<int4>(std::max<size_t>(1, tiles[si * (AXF_MAX_DEPTH + 1) + l].size()));
+            sz.add<int32_t>(std::max<size_t>(1, slots[si * (AXF_MAX_DEPTH + 1) + l].size()));
+        }
+    pl.tilemem = arena_acquire(sz.bytes + 4096);
+    for (int si = 0; si < 2; ++si) {
+        Side &s = *sides[si];
+        for (int l = 2; l <= pl.d; ++l) {
+            auto &tv = tiles[si * (AXF_MAX_DEPTH + 1) + l];
+            auto &sv = slots[si * (AXF_MAX_DEPTH + 1) + l];
+            s.tiles[l] = pl.tilemem.take<int4>(std::max<size_t>(1, tv.size()));
+            s.tile_slots[l] = pl.tilemem.take<int32_t>(std::max<size_t>(1, sv.size()));
+            s.ntiles[l] = (int)tv.size();
+            if (!tv.empty())
+                AXF_HIP(hipMemcpyAsync(s.tiles[l], tv.data(), tv.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+            if (!sv.empty())
+                AXF_HIP(hipMemcpyAsync(s.tile_slots[l], sv.data(), sv.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, st));
+        }
+    }
+    // the host vectors must outlive the copies
+    AXF_HIP(hipStreamSynchronize(st));
+    (void)bytes;
 }
 
 }  // namespace axf
