@@ -141,6 +141,18 @@ axf_status axf_plan_info(const axf_plan *plan, int32_t *depth, int32_t *n_modes,
 axf_status axf_plan_level_info(const axf_plan *plan, int32_t level,
                                int32_t *n_src_boxes, int32_t *n_fld_boxes);
 
+/* Copy one S2L Taylor table to host memory (App. A, eqs. gfunc:gnbar,
+ * gfunc:taylor, gfunc:scaled).  The table belongs to `level`, inner radial
+ * station `station` (0 <= station < 2^level) and box separation (dr, dz),
+ * 0 <= dr, dz <= 3, not both <= 1: with h the box width at the level,
+ * r_in = r_lo + (station + 1/2) h, r_out = r_in + dr h and x = dz h,
+ *     out[n][a][b][c] = c! * gbar^(n)_{a,b,c}(r_out, r_in, x) * h^(a+b+c)
+ * for a, b <= M and a + b + c <= 2M, zero elsewhere; host array of
+ * n_modes * (M+1) * (M+1) * (2M+1) doubles owned by the caller.
+ * Synchronous (waits for the plan's tables). */
+axf_status axf_plan_table(const axf_plan *plan, int32_t level, int32_t station, int32_t dr,
+                          int32_t dz, double *host_out);
+
 /* Phase timing.  When enabled, the library records HIP events on the calling
  * stream around every pass of axf_evaluate / axf_evaluate_grad /
  * axf_evaluate_direct / axf_adjoint and accumulates their durations

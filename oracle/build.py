@@ -10,7 +10,7 @@ def build() -> str:
     src = os.path.join(HERE, "oracle.c")
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
-           "-shared", src, "-o", tmp, "-lm"]
+           "-shared", src, "-o", tmp, "-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH

@@ -35,8 +35,13 @@
  *       clamped to 2^l - 1.
  *   R6. Moments i+j <= M, locals k+l <= M, derivative tables to total order
  *       2M: the S2L sum of eq. analysis:s2l runs over all i+j <= M.
+ *   R7. The starting formulas of App. A (eq. gfunc:derivatives:x and its r,
+ *       r1 and mixed companions) lose up to ~14 digits at high x order when
+ *       n x / r is small; they are evaluated in binary128 here (the paper
+ *       does not discuss their conditioning).
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -323,13 +328,107 @@ void ora_direct_adjoint(int64_t ns, const double *rs, const double *zs,
  * formulas are generated by the linear recurrence that multiplying through
  * by the denominator rho^2(x0+t) = rho^2 + 2 x0 t + t^2 gives. */
 
-/* u_q: Taylor coefficients of 1/(c^2 + x^2) about x0 */
-static void ora_inv_rho2_coeffs(double c, double x0, int Q, double *u)
+/* The starting columns (b <= 1 and a <= 1) are formed from sums and
+ * differences of neighbouring modes, (g^n + g^(n-1)) and (g^n - g^(n-1)).
+ * Where n x/r is small the two modes agree to many digits and the
+ * recurrence in k amplifies rounding errors by up to ~1e14 at order 2M = 48
+ * (measured against a 50-digit evaluation), so these columns, and the G^(n)
+ * they start from, are computed in IEEE binary128 (reading R7).  The Laplace
+ * recursion that fills the rest of the table is well conditioned and runs in
+ * FP64. */
+typedef __float128 ora_q;
+
+static ora_q ora_rf_q(ora_q x, ora_q y, ora_q z)
 {
-    double rho2 = c * c + x0 * x0;
-    u[0] = 1.0 / rho2;
-    if (Q >= 1) u[1] = -2.0 * x0 * u[0] / rho2;
-    for (int q = 2; q <= Q; ++q) u[q] = -(2.0 * x0 * u[q - 1] + u[q - 2]) / rho2;
+    for (int it = 0; it < 400; ++it) {
+        ora_q A = (x + y + z) / 3;
+        ora_q X = 1 - x / A, Y = 1 - y / A, Z = 1 - z / A;
+        ora_q dev = fmaxq(fabsq(X), fmaxq(fabsq(Y), fabsq(Z)));
+        if (dev < 1e-7Q) {   /* neglected sixth-order terms < 1e-40 */
+            ora_q E2 = X * Y - Z * Z;
+            ora_q E3 = X * Y * Z;
+            return (1 - E2 / 10 + E3 / 14 + E2 * E2 / 24 - 3 * E2 * E3 / 44) / sqrtq(A);
+        }
+        ora_q sx = sqrtq(x), sy = sqrtq(y), sz = sqrtq(z);
+        ora_q lam = sx * sy + sy * sz + sz * sx;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        z = (z + lam) / 4;
+    }
+    return nanq("");
+}
+
+static ora_q ora_rd_q(ora_q x, ora_q y, ora_q z)
+{
+    ora_q sum = 0, scale = 1;
+    for (int it = 0; it < 400; ++it) {
+        ora_q A = (x + y + 3 * z) / 5;
+        ora_q X = 1 - x / A, Y = 1 - y / A, Z3 = 1 - z / A;
+        ora_q dev = fmaxq(fabsq(X), fmaxq(fabsq(Y), fabsq(Z3)));
+        if (dev < 1e-7Q) {
+            ora_q Z = -(X + Y) / 3;
+            ora_q XY = X * Y, Z2 = Z * Z;
+            ora_q E2 = XY - 6 * Z2;
+            ora_q E3 = (3 * XY - 8 * Z2) * Z;
+            ora_q E4 = 3 * (XY - Z2) * Z2;
+            ora_q E5 = XY * Z2 * Z;
+            ora_q ser = 1 - 3 * E2 / 14 + E3 / 6 + 9 * E2 * E2 / 88 - 3 * E4 / 22
+                        - 9 * E2 * E3 / 52 + 3 * E5 / 26;
+            return 3 * sum + scale * ser / (A * sqrtq(A));
+        }
+        ora_q sx = sqrtq(x), sy = sqrtq(y), sz = sqrtq(z);
+        ora_q lam = sx * sy + sy * sz + sz * sx;
+        sum += scale / (sz * (z + lam));
+        scale /= 4;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        z = (z + lam) / 4;
+    }
+    return nanq("");
+}
+
+/* G^(n), n = 0..N, in binary128: the steps of ora_qseq / ora_green with the
+ * backward-recursion start lengthened for the smaller target error
+ * (e^(-2 eta (ntop - N)) < 1e-34). */
+static void ora_green_q(int N, ora_q r, ora_q r1, ora_q x, ora_q *G)
+{
+    ora_q dr = r - r1, sr = r + r1;
+    ora_q rm2 = dr * dr + x * x, rp2 = sr * sr + x * x, rr = r * r1;
+    ora_q dchi = rm2 / (2 * rr), chi = 1 + dchi;
+    ora_q m = 4 * rr / rp2, mc = rm2 / rp2;
+    ora_q rf = ora_rf_q(0, mc, 1);
+    ora_q K = rf, E = rf - (m / 3) * ora_rd_q(0, mc, 1);
+    ora_q mu = sqrtq(m);
+    G[0] = mu * K;
+    if (N >= 1) {
+        if (chi < 1.008Q) {
+            G[1] = chi * mu * K - (1 + chi) * mu * E;
+            for (int n = 1; n < N; ++n)
+                G[n + 1] = (4 * n * chi * G[n] - (2 * n - 1) * G[n - 1]) / (2 * n + 1);
+        } else {
+            ora_q eta = log1pq(dchi + sqrtq(dchi * (2 + dchi)));
+            int extra = (int)ceilq(40 / eta) + 10;
+            if (extra < 160) extra = 160;
+            int ntop = N + extra;
+            ora_q *t = (ora_q *)malloc(sizeof(ora_q) * (size_t)(ntop + 1));
+            t[ntop] = 0;
+            for (int n = ntop; n >= 1; --n)
+                t[n - 1] = (2 * n - 1) / (4 * n * chi - (2 * n + 1) * t[n]);
+            for (int n = 0; n < N; ++n) G[n + 1] = t[n] * G[n];
+            free(t);
+        }
+    }
+    ora_q f = 1 / (2 * M_PIq * sqrtq(rr));
+    for (int n = 0; n <= N; ++n) G[n] *= f;
+}
+
+/* u_q: Taylor coefficients of 1/(c^2 + x^2) about x0 */
+static void ora_inv_rho2_coeffs(ora_q c, ora_q x0, int Q, ora_q *u)
+{
+    ora_q rho2 = c * c + x0 * x0;
+    u[0] = 1 / rho2;
+    if (Q >= 1) u[1] = -2 * x0 * u[0] / rho2;
+    for (int q = 2; q <= Q; ++q) u[q] = -(2 * x0 * u[q - 1] + u[q - 2]) / rho2;
 }
 
 #define TIDX(n, a, b, c) ((((size_t)(n) * (M + 1) + (a)) * (M + 1) + (b)) * (2 * M + 1) + (c))
@@ -340,53 +439,58 @@ void ora_gtable(int N, int M, double r, double r1, double x, double *T)
     int K = 2 * M;               /* highest x order */
     size_t per = (size_t)(M + 1) * (M + 1) * (2 * M + 1);
     double *W = (double *)calloc(per * (size_t)(Nw + 1), sizeof(double));
-    double G[Nw + 1];
-    ora_green(Nw, r, r1, x, G);
+    ora_q Gq[Nw + 1];
+    ora_q rq = r, r1q = r1, xq = x;
+    ora_green_q(Nw, rq, r1q, xq, Gq);
 
-    double cp = r + r1, cm = r - r1;
-    double up[K + 1], um[K + 1];
-    ora_inv_rho2_coeffs(cp, x, K, up);
-    ora_inv_rho2_coeffs(cm, x, K, um);
+    ora_q cp = rq + r1q, cm = rq - r1q;
+    ora_q up[K + 1], um[K + 1];
+    ora_inv_rho2_coeffs(cp, xq, K, up);
+    ora_inv_rho2_coeffs(cm, xq, K, um);
     /* f = x / rho^2, numerator x0 + t */
-    double fp[K + 1], fm[K + 1];
+    ora_q fp[K + 1], fm[K + 1];
     /* p = (r^2 - r1^2 - x^2) / rho^2, numerator A0 - 2 x0 t - t^2 */
-    double pp[K + 1], pm[K + 1], qp[K + 1], qm[K + 1];  /* q: r <-> r1 exchanged */
-    double A0 = r * r - r1 * r1 - x * x, B0 = r1 * r1 - r * r - x * x;
+    ora_q pp[K + 1], pm[K + 1], qp[K + 1], qm[K + 1];  /* q: r <-> r1 exchanged */
+    ora_q A0 = rq * rq - r1q * r1q - xq * xq, B0 = r1q * r1q - rq * rq - xq * xq;
     for (int q = 0; q <= K; ++q) {
-        double um1p = q >= 1 ? up[q - 1] : 0.0, um2p = q >= 2 ? up[q - 2] : 0.0;
-        double um1m = q >= 1 ? um[q - 1] : 0.0, um2m = q >= 2 ? um[q - 2] : 0.0;
-        fp[q] = x * up[q] + um1p;
-        fm[q] = x * um[q] + um1m;
-        pp[q] = A0 * up[q] - 2.0 * x * um1p - um2p;
-        pm[q] = A0 * um[q] - 2.0 * x * um1m - um2m;
-        qp[q] = B0 * up[q] - 2.0 * x * um1p - um2p;
-        qm[q] = B0 * um[q] - 2.0 * x * um1m - um2m;
+        ora_q um1p = q >= 1 ? up[q - 1] : 0, um2p = q >= 2 ? up[q - 2] : 0;
+        ora_q um1m = q >= 1 ? um[q - 1] : 0, um2m = q >= 2 ? um[q - 2] : 0;
+        fp[q] = xq * up[q] + um1p;
+        fm[q] = xq * um[q] + um1m;
+        pp[q] = A0 * up[q] - 2 * xq * um1p - um2p;
+        pm[q] = A0 * um[q] - 2 * xq * um1m - um2m;
+        qp[q] = B0 * up[q] - 2 * xq * um1p - um2p;
+        qm[q] = B0 * um[q] - 2 * xq * um1m - um2m;
     }
     /* d = d/dr1 of p: (-2 r1)/rho^2 - p * (d rho^2/dr1)/rho^2,
      * d rho+^2/dr1 = 2 (r + r1), d rho-^2/dr1 = -2 (r - r1). */
-    double dp[K + 1], dm[K + 1];
+    ora_q dp[K + 1], dm[K + 1];
     for (int q = 0; q <= K; ++q) {
-        double cpu = 0.0, cmu = 0.0;
+        ora_q cpu = 0, cmu = 0;
         for (int s = 0; s <= q; ++s) {
             cpu += pp[s] * up[q - s];
             cmu += pm[s] * um[q - s];
         }
-        dp[q] = -2.0 * r1 * up[q] - 2.0 * cp * cpu;
-        dm[q] = -2.0 * r1 * um[q] + 2.0 * cm * cmu;
+        dp[q] = -2 * r1q * up[q] - 2 * cp * cpu;
+        dm[q] = -2 * r1q * um[q] + 2 * cm * cmu;
     }
 
-#define WI(n, a, b, c) W[(size_t)(n) * per + ((size_t)(a) * (M + 1) + (b)) * (2 * M + 1) + (c)]
+    /* starting columns in binary128: g00[n][k], g10, g01, g11 */
+    size_t col = (size_t)(Nw + 1) * (K + 1);
+    ora_q *g00 = (ora_q *)calloc(4 * col, sizeof(ora_q));
+    ora_q *g10 = g00 + col, *g01 = g10 + col, *g11 = g01 + col;
+#define GQ(a, n, k) a[(size_t)(n) * (K + 1) + (k)]
     /* x-derivatives, eq. gfunc:derivatives:x, k-outer / n-inner */
-    for (int n = 0; n <= Nw; ++n) WI(n, 0, 0, 0) = G[n];
+    for (int n = 0; n <= Nw; ++n) GQ(g00, n, 0) = Gq[n];
     for (int k = 0; k < K; ++k) {
         for (int n = 0; n <= Nw; ++n) {
             int nm = n == 0 ? 1 : n - 1;
-            double s = 0.0;
+            ora_q s = 0;
             for (int q = 0; q <= k; ++q) {
-                double gn = WI(n, 0, 0, k - q), gm = WI(nm, 0, 0, k - q);
+                ora_q gn = GQ(g00, n, k - q), gm = GQ(g00, nm, k - q);
                 s += (gn + gm) * fp[q] + (gn - gm) * fm[q];
             }
-            WI(n, 0, 0, k + 1) = (n - 0.5) * s / (k + 1.0);
+            GQ(g00, n, k + 1) = (n - 0.5Q) * s / (k + 1);
         }
     }
     if (M >= 1) {
@@ -394,31 +498,43 @@ void ora_gtable(int N, int M, double r, double r1, double x, double *T)
         for (int n = 0; n <= Nw; ++n) {
             int nm = n == 0 ? 1 : n - 1;
             for (int k = 0; k <= K - 1; ++k) {
-                double s1 = 0.0, s2 = 0.0;
+                ora_q s1 = 0, s2 = 0;
                 for (int q = 0; q <= k; ++q) {
-                    double gn = WI(n, 0, 0, k - q), gm = WI(nm, 0, 0, k - q);
+                    ora_q gn = GQ(g00, n, k - q), gm = GQ(g00, nm, k - q);
                     s1 += (gn + gm) * pp[q] + (gn - gm) * pm[q];
                     s2 += (gn + gm) * qp[q] + (gn - gm) * qm[q];
                 }
-                WI(n, 1, 0, k) = -WI(n, 0, 0, k) / (2.0 * r) + (n - 0.5) / (2.0 * r) * s1;
-                WI(n, 0, 1, k) = -WI(n, 0, 0, k) / (2.0 * r1) + (n - 0.5) / (2.0 * r1) * s2;
+                GQ(g10, n, k) = -GQ(g00, n, k) / (2 * rq) + (n - 0.5Q) / (2 * rq) * s1;
+                GQ(g01, n, k) = -GQ(g00, n, k) / (2 * r1q) + (n - 0.5Q) / (2 * r1q) * s2;
             }
         }
         /* mixed r, r1 derivative */
         for (int n = 0; n <= Nw; ++n) {
             int nm = n == 0 ? 1 : n - 1;
             for (int k = 0; k <= K - 2; ++k) {
-                double s = 0.0;
+                ora_q s = 0;
                 for (int q = 0; q <= k; ++q) {
-                    double gn = WI(n, 0, 0, k - q), gm = WI(nm, 0, 0, k - q);
-                    double hn = WI(n, 0, 1, k - q), hm = WI(nm, 0, 1, k - q);
+                    ora_q gn = GQ(g00, n, k - q), gm = GQ(g00, nm, k - q);
+                    ora_q hn = GQ(g01, n, k - q), hm = GQ(g01, nm, k - q);
                     s += (gn + gm) * dp[q] + (hn + hm) * pp[q]
                          + (gn - gm) * dm[q] + (hn - hm) * pm[q];
                 }
-                WI(n, 1, 1, k) = -WI(n, 0, 1, k) / (2.0 * r) + (n - 0.5) / (2.0 * r) * s;
+                GQ(g11, n, k) = -GQ(g01, n, k) / (2 * rq) + (n - 0.5Q) / (2 * rq) * s;
             }
         }
     }
+#define WI(n, a, b, c) W[(size_t)(n) * per + ((size_t)(a) * (M + 1) + (b)) * (2 * M + 1) + (c)]
+    for (int n = 0; n <= Nw; ++n)
+        for (int k = 0; k <= K; ++k) {
+            WI(n, 0, 0, k) = (double)GQ(g00, n, k);
+            if (M >= 1 && k <= K - 1) {
+                WI(n, 1, 0, k) = (double)GQ(g10, n, k);
+                WI(n, 0, 1, k) = (double)GQ(g01, n, k);
+            }
+            if (M >= 1 && k <= K - 2) WI(n, 1, 1, k) = (double)GQ(g11, n, k);
+        }
+#undef GQ
+    free(g00);
     /* Laplace recursion (eq. gfunc:laplace, reading R1) in r for b = 0, 1,
      * then in r1 for all a. */
     for (int n = 0; n <= N; ++n) {
@@ -577,11 +693,28 @@ static void ora_pair_kernel(int N, double r, double r1, double x, double *G, int
     }
 }
 
+void ora_fmm_grad(int64_t ns, const double *rs, const double *zs,
+                  int64_t nf, const double *rf, const double *zf,
+                  int nmodes, int nrhs, const double *S, int M, int depth, int flags,
+                  double *phi, double *dphi_dr, double *dphi_dz);
+
 void ora_fmm(int64_t ns, const double *rs, const double *zs,
              int64_t nf, const double *rf, const double *zf,
              int nmodes, int nrhs, const double *S, int M, int depth, int flags,
              double *phi)
 {
+    ora_fmm_grad(ns, rs, zs, nf, rf, zf, nmodes, nrhs, S, M, depth, flags, phi, NULL, NULL);
+}
+
+/* Algorithm 1 with, optionally, the field gradient at the field points:
+ * the r- and z-derivatives of the local expansion (eq. analysis:local) plus
+ * the near-field sum of S dG/dr and S dG/dx (App. A starting formulas). */
+void ora_fmm_grad(int64_t ns, const double *rs, const double *zs,
+                  int64_t nf, const double *rf, const double *zf,
+                  int nmodes, int nrhs, const double *S, int M, int depth, int flags,
+                  double *phi, double *dphi_dr, double *dphi_dz)
+{
+    int grad = dphi_dr != NULL && dphi_dz != NULL;
     int unit = flags & 1;
     int N = nmodes - 1, d = depth;
     int P = (M + 1) * (M + 2) / 2;
@@ -721,43 +854,53 @@ void ora_fmm(int64_t ns, const double *rs, const double *zs,
         double h = sq.L / nb;
 #pragma omp parallel
         {
-            double *G = malloc(sizeof(double) * nmodes);
+            double *G = malloc(sizeof(double) * nmodes), *Gr = malloc(sizeof(double) * nmodes);
+            double *Gr1 = malloc(sizeof(double) * nmodes), *Gx = malloc(sizeof(double) * nmodes);
 #pragma omp for schedule(dynamic, 16)
             for (int64_t j = 0; j < nf; ++j) {
                 double rc = sq.rlo + (fir[j] + 0.5) * h, zc = sq.zlo + (fiz[j] + 0.5) * h;
                 double dr = rf[j] - rc, dz = zf[j] - zc;
                 const double *lc = loc[d] + blk * ((size_t)fir[j] * nb + fiz[j]);
                 for (int c = 0; c < C; ++c) {
-                    double are = 0.0, aim = 0.0, pr = 1.0;
-                    for (int k = 0; k <= M; ++k) {
-                        double pz = 1.0;
+                    double are = 0.0, aim = 0.0, gre = 0.0, gim = 0.0, zre = 0.0, zim = 0.0;
+                    for (int k = 0; k <= M; ++k)
                         for (int l2 = 0; k + l2 <= M; ++l2) {
-                            double w = unit ? (k == 0 && l2 == 0 ? 1.0 : 0.0) : pr * pz;
-                            are += w * lc[2 * ((size_t)P * c + ora_tri(M, k, l2))];
-                            aim += w * lc[2 * ((size_t)P * c + ora_tri(M, k, l2)) + 1];
-                            pz *= dz;
+                            double w = unit ? (k == 0 && l2 == 0 ? 1.0 : 0.0) : pow(dr, k) * pow(dz, l2);
+                            double wr = (k > 0 && !unit) ? k * pow(dr, k - 1) * pow(dz, l2) : 0.0;
+                            double wz = (l2 > 0 && !unit) ? l2 * pow(dr, k) * pow(dz, l2 - 1) : 0.0;
+                            const double *v = lc + 2 * ((size_t)P * c + ora_tri(M, k, l2));
+                            are += w * v[0]; aim += w * v[1];
+                            gre += wr * v[0]; gim += wr * v[1];
+                            zre += wz * v[0]; zim += wz * v[1];
                         }
-                        pr *= dr;
-                    }
                     int q = c / nmodes, n = c % nmodes;
-                    double *p = phi + 2 * (((int64_t)q * nmodes + n) * nf + j);
-                    p[0] = are;
-                    p[1] = aim;
+                    int64_t o = 2 * (((int64_t)q * nmodes + n) * nf + j);
+                    phi[o] = are;
+                    phi[o + 1] = aim;
+                    if (grad) {
+                        dphi_dr[o] = gre; dphi_dr[o + 1] = gim;
+                        dphi_dz[o] = zre; dphi_dz[o + 1] = zim;
+                    }
                 }
                 for (int64_t i = 0; i < ns; ++i) {
                     if (abs(sir[i] - fir[j]) > 1 || abs(siz[i] - fiz[j]) > 1) continue;
                     if (rs[i] == rf[j] && zs[i] == zf[j]) continue;
-                    ora_pair_kernel(N, rf[j], rs[i], zf[j] - zs[i], G, unit);
+                    if (grad) ora_green_d1(N, rf[j], rs[i], zf[j] - zs[i], G, Gr, Gr1, Gx);
+                    else ora_pair_kernel(N, rf[j], rs[i], zf[j] - zs[i], G, unit);
                     for (int q = 0; q < nrhs; ++q)
                         for (int n = 0; n <= N; ++n) {
-                            const double *s = S + 2 * (((int64_t)q * nmodes + n) * ns + i);
-                            double *p = phi + 2 * (((int64_t)q * nmodes + n) * nf + j);
-                            p[0] += s[0] * G[n];
-                            p[1] += s[1] * G[n];
+                            const double *sv = S + 2 * (((int64_t)q * nmodes + n) * ns + i);
+                            int64_t o = 2 * (((int64_t)q * nmodes + n) * nf + j);
+                            phi[o] += sv[0] * G[n];
+                            phi[o + 1] += sv[1] * G[n];
+                            if (grad) {
+                                dphi_dr[o] += sv[0] * Gr[n]; dphi_dr[o + 1] += sv[1] * Gr[n];
+                                dphi_dz[o] += sv[0] * Gx[n]; dphi_dz[o + 1] += sv[1] * Gx[n];
+                            }
                         }
                 }
             }
-            free(G);
+            free(G); free(Gr); free(Gr1); free(Gx);
         }
     }
     for (int l = 2; l <= d; ++l) { free(mom[l]); free(loc[l]); }

@@ -44,11 +44,13 @@ def _load():
                                     ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]
     lib.ora_fmm.argtypes = common + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+    lib.ora_fmm_grad.argtypes = common + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     lib.ora_fmm_points.argtypes = common + [ctypes.c_int, ctypes.c_int, _i64,
                                             ctypes.POINTER(ctypes.c_int64), _dp]
     for f in (lib.ora_qseq, lib.ora_green, lib.ora_direct, lib.ora_direct_grad,
               lib.ora_direct_adjoint, lib.ora_gtable, lib.ora_square_info,
-              lib.ora_box_indices, lib.ora_fmm, lib.ora_fmm_points, lib.ora_ellipke):
+              lib.ora_box_indices, lib.ora_fmm, lib.ora_fmm_points, lib.ora_ellipke,
+              lib.ora_fmm_grad):
         f.restype = None
     _lib = lib
     return lib
@@ -174,6 +176,20 @@ def fmm(rs, zs, rf, zf, S, M: int, depth: int, unit_kernel: bool = False):
     lib.ora_fmm(ns, _p(rs), _p(zs), rf.size, _p(rf), _p(zf), nmodes, nrhs, _p(S),
                 M, depth, 1 if unit_kernel else 0, _p(phi))
     return phi
+
+
+def fmm_grad(rs, zs, rf, zf, S, M: int, depth: int):
+    """Reference FMM with the gradient of the field: (phi, dphi/dr, dphi/dz)."""
+    lib = _load()
+    rs, zs, rf, zf = map(_f64, (rs, zs, rf, zf))
+    S = _c128(S)
+    nrhs, nmodes, ns = S.shape
+    phi = np.zeros((nrhs, nmodes, rf.size), dtype=np.complex128)
+    dr = np.zeros_like(phi)
+    dz = np.zeros_like(phi)
+    lib.ora_fmm_grad(ns, _p(rs), _p(zs), rf.size, _p(rf), _p(zf), nmodes, nrhs, _p(S),
+                     M, depth, 0, _p(phi), _p(dr), _p(dz))
+    return phi, dr, dz
 
 
 def fmm_points(rs, zs, rf, zf, S, M: int, depth: int, idx):

@@ -24,7 +24,7 @@ EXPORTED = [
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
     "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
-    "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work",
+    "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
 ]
 
 PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct"]
@@ -86,10 +86,11 @@ def load_library(path: str = LIB_PATH):
     lib.axf_plan_set_timing.argtypes = [vp, i32]
     lib.axf_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i32)]
     lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(ctypes.c_double)]
+    lib.axf_plan_table.argtypes = [vp, i32, i32, i32, i32, P(ctypes.c_double)]
     for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
                  "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
-                 "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work"):
+                 "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -189,6 +190,16 @@ class Plan:
         return {"near_pairs": near.value, "s2l_pairs": s2l.value,
                 "flops": {p: fl[i] for i, p in enumerate(PHASES)}}
 
+    def table(self, level: int, station: int, dr: int, dz: int):
+        """The stored S2L table of (level, inner station, separation) as a
+        numpy array [n_modes, M+1, M+1, 2M+1]: c! gbar_{a,b,c} h^(a+b+c)."""
+        import numpy as np
+        M = self.order
+        out = np.zeros((self.n_modes, M + 1, M + 1, 2 * M + 1))
+        _check(_lib.axf_plan_table(self._h, level, station, dr, dz,
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "axf_plan_table")
+        return out
+
     # ------------------------------------------------------- evaluation
     def _strengths(self, S, n):
         S = torch.as_tensor(S, device=self.device)
@@ -234,6 +245,80 @@ class Plan:
         _check(_lib.axf_adjoint(self._h, _ptr(Sp), _ptr(gphi), _ptr(gS), _ptr(gr), _ptr(gz), _stream()),
                "axf_adjoint")
         return gS, gr, gz
+
+
+class Batch:
+    """Many independent problems evaluated by one captured launch sequence.
+
+    problems: sequence of (r_src, z_src, r_fld, z_fld, S) or
+    (r_src, z_src, r_fld, z_fld, S, depth); S complex [nrhs, n_modes, ns].
+    Depth 0 lets the library's autotuner choose (or the max_leaf rule when
+    autotune is False).  The strength tensors are kept and read at every
+    launch, so they may be updated in place between launches; `outputs`
+    holds the potentials [nrhs, n_modes, nf] of each problem.
+    """
+
+    def __init__(self, problems, n_modes: int, order: int, max_leaf: int = 64,
+                 autotune: bool = True, device=None):
+        lib = load_library()
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.n_modes, self.order = n_modes, order
+        self._keep = []
+        self.strengths, self.outputs = [], []
+        arr = (Problem * len(problems))()
+        for i, pb in enumerate(problems):
+            rs, zs, rf, zf, S = pb[:5]
+            depth = pb[5] if len(pb) > 5 else 0
+            rs, zs, rf, zf = (_coords(a, dev) for a in (rs, zs, rf, zf))
+            S = torch.as_tensor(S, device=dev).to(torch.complex128)
+            if S.dim() == 2:
+                S = S.unsqueeze(0)
+            S = S.contiguous()
+            nrhs = S.shape[0]
+            if S.shape != (nrhs, n_modes, rs.numel()):
+                raise ValueError(f"problem {i}: S must be [nrhs, {n_modes}, {rs.numel()}]")
+            phi = torch.empty((nrhs, n_modes, rf.numel()), dtype=torch.complex128, device=dev)
+            arr[i] = Problem(rs.numel(), rf.numel(), rs.data_ptr(), zs.data_ptr(), rf.data_ptr(),
+                             zf.data_ptr(), S.data_ptr(), phi.data_ptr(), nrhs, depth)
+            self._keep.append((rs, zs, rf, zf))
+            self.strengths.append(S)
+            self.outputs.append(phi)
+        p = Params(n_modes, order, 0, max_leaf, 1, 0 if autotune else 1)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = lib.axf_batch_create(ctypes.byref(p), len(problems), arr, _stream(), ctypes.byref(h))
+        _check(st, "axf_batch_create")
+        self._h = h
+
+    def launch(self):
+        """Replay the captured graph on the current stream."""
+        _check(_lib.axf_batch_launch(self._h, _stream()), "axf_batch_launch")
+        return self.outputs
+
+    def launch_plain(self):
+        """Per-problem launches without the graph or merged queues."""
+        _check(_lib.axf_batch_launch_plain(self._h, _stream()), "axf_batch_launch_plain")
+        return self.outputs
+
+    def depths(self):
+        out = []
+        for i in range(len(self.outputs)):
+            d = ctypes.c_int32()
+            _check(_lib.axf_batch_problem_depth(self._h, i, ctypes.byref(d)), "axf_batch_problem_depth")
+            out.append(d.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.axf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class AxFMM(torch.autograd.Function):

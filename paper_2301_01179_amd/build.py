@@ -23,9 +23,14 @@ FLAGS = [
 ]
 
 
+# Per-file flags.  The table builder's double-double arithmetic needs every
+# product and sum rounded on its own (no fused multiply-add contraction).
+FILE_FLAGS = {"axf_tables.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

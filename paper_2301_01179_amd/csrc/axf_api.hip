@@ -119,7 +119,7 @@ static void release_events(Plan *pl)
     pl->spare_events.clear();
 }
 
-static void plan_release(Plan *pl)
+void plan_release(Plan *pl)
 {
     if (!pl) return;
     (void)hipDeviceSynchronize();
@@ -336,6 +336,33 @@ axf_status axf_plan_level_info(const axf_plan *plan, int32_t level, int32_t *n_s
         AXF_REQUIRE(level >= 2 && level <= plan->pl.d, AXF_ERR_INVALID_ARGUMENT, "level out of range");
         if (n_src_boxes) *n_src_boxes = plan->pl.src.nocc[level];
         if (n_fld_boxes) *n_fld_boxes = plan->pl.fld.nocc[level];
+    })
+}
+
+axf_status axf_plan_table(const axf_plan *plan, int32_t level, int32_t station, int32_t dr, int32_t dz,
+                          double *host_out)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && host_out, AXF_ERR_INVALID_ARGUMENT, "plan and host_out must be non-NULL");
+        const Plan &pl = plan->pl;
+        AXF_REQUIRE(level >= 2 && level <= pl.d, AXF_ERR_INVALID_ARGUMENT, "level out of range");
+        AXF_REQUIRE(station >= 0 && station < (1 << level), AXF_ERR_INVALID_ARGUMENT, "station out of range");
+        AXF_REQUIRE(dr >= 0 && dr <= 3 && dz >= 0 && dz <= 3 && (dr >= 2 || dz >= 2), AXF_ERR_INVALID_ARGUMENT,
+                    "separation must satisfy 0 <= dr, dz <= 3, not both <= 1");
+        const int M = pl.M, K = 2 * M, nm = pl.nmodes;
+        const size_t TS = (size_t)pl.TS;
+        std::vector<double> buf(TS * nm);
+        const double *src = pl.lev[level].tab + ((size_t)station * 12 + geom_slot(dr, dz)) * nm * TS;
+        AXF_HIP(hipSetDevice(pl.device));
+        AXF_HIP(hipDeviceSynchronize());
+        AXF_HIP(hipMemcpy(buf.data(), src, sizeof(double) * TS * nm, hipMemcpyDeviceToHost));
+        for (int n = 0; n < nm; ++n)
+            for (int a = 0; a <= M; ++a)
+                for (int b = 0; b <= M; ++b)
+                    for (int c = 0; c <= K; ++c) {
+                        double v = (a + b + c <= K) ? buf[(size_t)n * TS + table_row(M, a, b) + c] : 0.0;
+                        host_out[(((size_t)n * (M + 1) + a) * (M + 1) + b) * (K + 1) + c] = v;
+                    }
     })
 }
 

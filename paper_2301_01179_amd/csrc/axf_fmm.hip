@@ -20,10 +20,6 @@ namespace {
 
 constexpr int kMaxRhs = AXF_MAX_RHS;
 
-struct SideView {     // device-side view of a Side
-    const double *r, *z;
-    const int32_t *perm, *off;
-};
 
 // ---------------------------------------------------------------- gather
 // Strengths into tree order, point-major with Cs = nmb * nrhs channels per
@@ -41,14 +37,14 @@ __global__ void k_gather(const double2 *__restrict__ S, const int32_t *__restric
 
 // ------------------------------------------------------------------- P2M
 constexpr int kP2MChunk = 32;
-__global__ __launch_bounds__(256) void k_p2m(int M, int C, int Cs, int depth, double rlo, double zlo,
-                                            double invh, SideView sv, const int32_t *__restrict__ boxes,
-                                            const double2 *__restrict__ Sg, double2 *__restrict__ mom)
+__device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double rlo, double zlo, double invh,
+                                         SideView sv, const int32_t *__restrict__ boxes,
+                                         const double2 *__restrict__ Sg, double2 *__restrict__ mom, int item)
 {
     __shared__ double pr[kP2MChunk][AXF_MAX_ORDER + 1];
     __shared__ double pz[kP2MChunk][AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
-    const int k = blockIdx.x;
+    const int k = item;
     const int b = boxes[k];
     const int nb = 1 << depth;
     const int ir = b / nb, iz = b - ir * nb;
@@ -124,17 +120,24 @@ __global__ __launch_bounds__(256) void k_p2m(int M, int C, int Cs, int depth, do
     }
 }
 
+__global__ __launch_bounds__(256) void k_p2m(int M, int C, int Cs, int depth, double rlo, double zlo,
+                                            double invh, SideView sv, const int32_t *__restrict__ boxes,
+                                            const double2 *__restrict__ Sg, double2 *__restrict__ mom)
+{
+    p2m_body(M, C, Cs, depth, rlo, zlo, invh, sv, boxes, Sg, mom, blockIdx.x);
+}
+
 // ------------------------------------------------------------------- M2M
 // parent s_ij = sum_children sum_a C(i,a) dr^(i-a) 2^-a sum_b dz^(j-b)/(j-b)! 2^-b s'_ab
 // with dr, dz = +-1/4 (child centre - parent centre in parent units).
-__global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int32_t *__restrict__ pboxes,
-                                            const int32_t *__restrict__ cslot,
-                                            const double2 *__restrict__ cmom, double2 *__restrict__ pmom)
+__device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t *__restrict__ pboxes,
+                                         const int32_t *__restrict__ cslot, const double2 *__restrict__ cmom,
+                                         double2 *__restrict__ pmom, int item)
 {
     __shared__ double cfr[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
     __shared__ double cfz[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
-    const int k = blockIdx.x;
+    const int k = item;
     const int b = pboxes[k];
     const int nb = 1 << level;
     const int ir = b / nb, iz = b - ir * nb;
@@ -193,135 +196,11 @@ __global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int3
     }
 }
 
-// --------------------------------------------------------- L2L + S2L
-// One block per (occupied target box, mode).
-__global__ __launch_bounds__(256) void k_s2l(int M, int nmodes, int nrhs, int level, int TS,
-                                            const int32_t *__restrict__ tboxes,
-                                            const int32_t *__restrict__ tslot_parent,
-                                            const double2 *__restrict__ ploc,
-                                            const int32_t *__restrict__ sslot,
-                                            const double2 *__restrict__ mom,
-                                            const double *__restrict__ tab,
-                                            double2 *__restrict__ loc)
+__global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int32_t *__restrict__ pboxes,
+                                            const int32_t *__restrict__ cslot,
+                                            const double2 *__restrict__ cmom, double2 *__restrict__ pmom)
 {
-    extern __shared__ double2 ms[];          // [nrhs][P] staged moments
-    __shared__ double lcoef[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];   // L2L factors
-    __shared__ double invfact[AXF_MAX_ORDER + 1];
-    const int P = (M + 1) * (M + 2) / 2;
-    const int C = nmodes * nrhs;
-    const int k = blockIdx.x / nmodes, n = blockIdx.x - (blockIdx.x / nmodes) * nmodes;
-    const int b = tboxes[k];
-    const int nb = 1 << level;
-    const int ir = b / nb, iz = b - ir * nb;
-    const int tid = threadIdx.x;
-
-    if (tid <= M) {
-        double f = 1.0;
-        for (int t = 2; t <= tid; ++t) f *= t;
-        invfact[tid] = 1.0 / f;
-    }
-    // L2L factors: C(i+q, q) d^q 2^-(i) for d = -1/4, +1/4 (child - parent, parent units)
-    for (int e = tid; e < 2 * (M + 1) * (M + 1); e += blockDim.x) {
-        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
-        int i = rem / (M + 1), q = rem - i * (M + 1);
-        double d = sg ? 0.25 : -0.25;
-        double v = 0.0;
-        if (i + q <= M) {
-            double bin = 1.0;
-            for (int t = 0; t < q; ++t) bin = bin * (i + q - t) / (t + 1.0);
-            double pw = 1.0;
-            for (int t = 0; t < q; ++t) pw *= d;
-            v = bin * pw * ldexp(1.0, -i);
-        }
-        lcoef[sg][i][q] = v;
-    }
-    // outputs of this thread
-    int ok[2], ol[2];
-    bool act[2];
-    for (int u = 0; u < 2; ++u) {
-        int p = tid + u * 256;
-        act[u] = p < P;
-        int kk = 0;
-        if (act[u]) {
-            while (p >= M + 1 - kk) {
-                p -= M + 1 - kk;
-                ++kk;
-            }
-        }
-        ok[u] = kk;
-        ol[u] = act[u] ? p : 0;
-    }
-    double2 acc[2][kMaxRhs];
-    for (int u = 0; u < 2; ++u)
-        for (int q = 0; q < kMaxRhs; ++q) acc[u][q] = make_double2(0.0, 0.0);
-    __syncthreads();
-
-    const double *tab_n = tab + (size_t)n * TS;
-    const int jr0 = 2 * (ir >> 1) - 2, jz0 = 2 * (iz >> 1) - 2;
-    for (int jr = jr0; jr < jr0 + 6; ++jr) {
-        if (jr < 0 || jr >= nb) continue;
-        for (int jz = jz0; jz < jz0 + 6; ++jz) {
-            if (jz < 0 || jz >= nb) continue;
-            if (abs(jr - ir) <= 1 && abs(jz - iz) <= 1) continue;
-            int ss = sslot[jr * nb + jz];
-            if (ss < 0) continue;
-            __syncthreads();
-            for (int e = tid; e < nrhs * P; e += blockDim.x) {
-                int q = e / P, p = e - q * P;
-                ms[e] = mom[((int64_t)ss * C + n * nrhs + q) * P + p];
-            }
-            __syncthreads();
-            const bool outward = jr <= ir;
-            const int station = outward ? jr : ir;
-            const int dr = outward ? ir - jr : jr - ir;
-            const int dz = abs(iz - jz);
-            const bool fwd = iz >= jz;
-            const double *T = tab_n + ((size_t)station * 12 + geom_slot(dr, dz)) * nmodes * (size_t)TS;
-            for (int u = 0; u < 2; ++u) {
-                if (!act[u]) continue;
-                const int kk = ok[u], ll = ol[u];
-                for (int i = 0; i <= M; ++i) {
-                    const double *row = T + (outward ? table_row(M, kk, i) : table_row(M, i, kk));
-                    const int pbase = tri_index(M, i, 0);
-                    for (int j = 0; j + i <= M; ++j) {
-                        int c = j + ll;
-                        double tv = row[c];
-                        if (fwd && (c & 1)) tv = -tv;
-                        for (int q = 0; q < nrhs; ++q) {
-                            double2 s = ms[q * P + pbase + j];
-                            acc[u][q].x += tv * s.x;
-                            acc[u][q].y += tv * s.y;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    // combine with the parent's shifted local expansion (eq. analysis:l2l)
-    int pslot = -1;
-    if (level > 2) pslot = tslot_parent[(ir >> 1) * (nb >> 1) + (iz >> 1)];
-    const int sr = ir & 1, sz = iz & 1;
-    for (int u = 0; u < 2; ++u) {
-        if (!act[u]) continue;
-        const int kk = ok[u], ll = ol[u];
-        const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
-        for (int q = 0; q < nrhs; ++q) {
-            double2 v = make_double2(f * acc[u][q].x, f * acc[u][q].y);
-            if (pslot >= 0) {
-                const double2 *pl = ploc + ((int64_t)pslot * C + n * nrhs + q) * P;
-                for (int a = 0; kk + a <= M; ++a) {
-                    double fa = lcoef[sr][kk][a];
-                    for (int c2 = 0; kk + a + ll + c2 <= M; ++c2) {
-                        double w = fa * lcoef[sz][ll][c2];
-                        double2 x = pl[tri_index(M, kk + a, ll + c2)];
-                        v.x += w * x.x;
-                        v.y += w * x.y;
-                    }
-                }
-            }
-            loc[((int64_t)k * C + n * nrhs + q) * P + tri_index(M, kk, ll)] = v;
-        }
-    }
+    m2m_body(M, C, level, pboxes, cslot, cmom, pmom, blockIdx.x);
 }
 
 // ------------------------------------------------------- S2L, tiled form
@@ -336,7 +215,7 @@ __global__ __launch_bounds__(256) void k_s2l(int M, int nmodes, int nrhs, int le
 // sign (-1)^(j+l) is split into (-1)^j on the staged moments and (-1)^l on
 // the accumulators.
 template <int LB, int TB>
-__global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
+__device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int level, int TS,
                                                  const int4 *__restrict__ tiles,      // station, parity, first, count
                                                  const int32_t *__restrict__ tslots,  // target slots of the tiles
                                                  const int32_t *__restrict__ tbox,    // slot -> box id (targets)
@@ -345,14 +224,14 @@ __global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, in
                                                  const int32_t *__restrict__ sslot,
                                                  const double2 *__restrict__ mom,
                                                  const double *__restrict__ tab,
-                                                 double2 *__restrict__ loc)
+                                                 double2 *__restrict__ loc, int item)
 {
     extern __shared__ double2 ms[];          // [TB][P] staged moments
     __shared__ double lcoef[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
     __shared__ double invfact[AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
-    const int ti = blockIdx.x / C, c = blockIdx.x - (blockIdx.x / C) * C;
+    const int ti = item / C, c = item - (item / C) * C;
     const int n = c / nrhs;
     const int4 tl = tiles[ti];
     const int station = tl.x, nbx = tl.w;
@@ -487,10 +366,9 @@ __global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, in
     }
     __syncthreads();
     // write: (-1)^l / l! * acc + parent's local shifted (eq. analysis:l2l)
-    if (!live) return;
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
-        if (sl[b] < 0) continue;
+        if (!live || sl[b] < 0) continue;
         const int bid = tbox[sl[b]];
         const int ir = bid / nb, iz = bid - ir * nb;
         int pslot = -1;
@@ -517,6 +395,19 @@ __global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, in
             loc[((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll)] = v;
         }
     }
+}
+
+template <int LB, int TB>
+__global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
+                                                 const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
+                                                 const int32_t *__restrict__ tbox,
+                                                 const int32_t *__restrict__ tslot_parent,
+                                                 const double2 *__restrict__ ploc, const int32_t *__restrict__ sslot,
+                                                 const double2 *__restrict__ mom, const double *__restrict__ tab,
+                                                 double2 *__restrict__ loc)
+{
+    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, tslot_parent, ploc, sslot, mom, tab,
+                          loc, blockIdx.x);
 }
 
 // ------------------------------------------------------------ pair sums
@@ -660,62 +551,71 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
     }
 }
 
-// Deterministic sum of the four waves' accumulators through LDS; wave 0
-// ends with the totals.  buf: [64][NMB] doubles per component.
-template <int NMB, int MODE>
-__device__ __forceinline__ void reduce_waves(Acc<NMB, MODE> &A, double *__restrict__ buf, int nmodes)
+// Launch shape of the pair kernels per mode bucket: waves per block (each
+// takes every WPB-th source) and sources per staged tile; larger buckets use
+// fewer waves so that the LDS scratch fits.
+template <int NMB>
+struct PairShape {
+    static constexpr int WPB = NMB <= 33 ? 4 : 2;
+    static constexpr int ST = NMB <= 33 ? 64 : 32;
+    static constexpr int RC = 16;       // modes per reduction round
+};
+
+// Deterministic sum of the block's waves' accumulators through LDS (in
+// rounds of RC modes); wave 0 ends with the totals.
+template <int NMB, int MODE, int WPB>
+__device__ __forceinline__ void reduce_waves(Acc<NMB, MODE> &A, double *__restrict__ buf)
 {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     constexpr int K = MODE ? 6 : 2;
-    for (int src = 3; src >= 1; --src) {
-        __syncthreads();
-        if (w == src) {
+    constexpr int RC = PairShape<NMB>::RC;
 #pragma unroll
-            for (int n = 0; n < NMB; ++n) {
-                if (n < nmodes) {
-                    double *b = buf + ((size_t)n * 64 + lane) * K;
+    for (int n0 = 0; n0 < NMB; n0 += RC) {
+        for (int src = WPB - 1; src >= 0; --src) {
+            __syncthreads();
+            if (w == src) {
+#pragma unroll
+                for (int n = n0; n < n0 + RC && n < NMB; ++n) {
+                    double *bp = buf + ((size_t)(n - n0) * 64 + lane) * K;
                     double v[6] = {A.ar[n], A.ai[n], 0, 0, 0, 0};
                     if constexpr (MODE != 0) {
                         v[2] = A.rr_[n]; v[3] = A.ri_[n]; v[4] = A.zr_[n]; v[5] = A.zi_[n];
                     }
-                    if (src == 3) {
-                        for (int k = 0; k < K; ++k) b[k] = v[k];
+                    if (src == WPB - 1) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) bp[k] = v[k];
+                    } else if (src > 0) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) bp[k] += v[k];
                     } else {
-                        for (int k = 0; k < K; ++k) b[k] += v[k];
+                        A.ar[n] += bp[0];
+                        A.ai[n] += bp[1];
+                        if constexpr (MODE != 0) {
+                            A.rr_[n] += bp[2]; A.ri_[n] += bp[3]; A.zr_[n] += bp[4]; A.zi_[n] += bp[5];
+                        }
                     }
                 }
             }
         }
     }
     __syncthreads();
-    if (w == 0) {
-#pragma unroll
-        for (int n = 0; n < NMB; ++n) {
-            if (n < nmodes) {
-                const double *b = buf + ((size_t)n * 64 + lane) * K;
-                A.ar[n] += b[0];
-                A.ai[n] += b[1];
-                if constexpr (MODE != 0) {
-                    A.rr_[n] += b[2]; A.ri_[n] += b[3]; A.zr_[n] += b[4]; A.zi_[n] += b[5];
-                }
-            }
-        }
-    }
 }
 
 template <int NMB, int MODE>
 constexpr size_t leaf_lds_doubles()
 {
-    size_t miller = (size_t)4 * NMB * 64;
-    size_t red = (size_t)64 * NMB * (MODE ? 6 : 2);
+    constexpr int WPB = PairShape<NMB>::WPB, RC = PairShape<NMB>::RC;
+    size_t miller = (size_t)WPB * NMB * 64;
+    size_t red = (size_t)64 * RC * (MODE ? 6 : 2);
     return miller > red ? miller : red;
 }
 
-// scratch + staged source tile (64 sources: strengths, r, z, 1/r)
+// scratch + staged source tile (strengths, r, z, 1/r)
 template <int NMB, int MODE>
 constexpr size_t leaf_lds_bytes()
 {
-    return leaf_lds_doubles<NMB, MODE>() * sizeof(double) + (size_t)64 * NMB * 16 + 3 * 64 * sizeof(double);
+    constexpr int ST = PairShape<NMB>::ST;
+    return leaf_lds_doubles<NMB, MODE>() * sizeof(double) + (size_t)ST * NMB * 16 + 3 * ST * sizeof(double);
 }
 
 // ------------------------------------------------------------ leaf pass
@@ -725,20 +625,21 @@ constexpr size_t leaf_lds_bytes()
 // MODE 0: potential; 1: potential and gradient; 2: potential and the
 // adjoint coordinate contraction.
 template <int NMB, int MODE>
-__global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int depth, double rlo, double zlo,
+__device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth, double rlo, double zlo,
                                              double invh, double chistar, const int4 *__restrict__ chunks,
                                              SideView tv, SideView sv, const double *__restrict__ sinv,
                                              const double2 *__restrict__ Sg, const double2 *__restrict__ loc,
                                              double2 *__restrict__ phi, double2 *__restrict__ dphr,
                                              double2 *__restrict__ dphz, const double2 *__restrict__ Sdot,
                                              double *__restrict__ gr, double *__restrict__ gz, int64_t ntot,
-                                             int Cs)
+                                             int Cs, int item)
 {
+    constexpr int WPB = PairShape<NMB>::WPB, ST = PairShape<NMB>::ST;
     extern __shared__ double lds[];
     double2 *st_S = reinterpret_cast<double2 *>(lds + leaf_lds_doubles<NMB, MODE>());
-    double *st_r = reinterpret_cast<double *>(st_S + 64 * NMB);
-    double *st_z = st_r + 64, *st_i = st_z + 64;
-    const int4 ch = chunks[blockIdx.x];
+    double *st_r = reinterpret_cast<double *>(st_S + ST * NMB);
+    double *st_z = st_r + ST, *st_i = st_z + ST;
+    const int4 ch = chunks[item];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const bool active = lane < ch.z;
     const int t = ch.y + (active ? lane : 0);
@@ -764,7 +665,7 @@ __global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int d
             for (int kk = 0; kk <= M; ++kk) {
                 double pz = 1.0, pz1 = 0.0;
                 for (int ll = 0; kk + ll <= M; ++ll, ++p) {
-                    if ((p & 3) == w) {
+                    if (p % WPB == w) {
                         const double wv = pr * pz;
 #pragma unroll
                         for (int n = 0; n < NMB; ++n) {
@@ -801,10 +702,10 @@ __global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int d
                 total += re[nr] - rb[nr];
                 ++nr;
             }
-        for (int tile = 0; tile < total; tile += 64) {
+        for (int tile = 0; tile < total; tile += ST) {
             __syncthreads();
-            const int cnt = min(64, total - tile);
-            for (int e = threadIdx.x; e < cnt * NMB; e += 256) {
+            const int cnt = min(ST, total - tile);
+            for (int e = threadIdx.x; e < cnt * NMB; e += 64 * WPB) {
                 const int k = e / NMB, n = e - k * NMB;
                 int li = tile + k, rr = 0;
                 while (li >= re[rr] - rb[rr]) {
@@ -820,13 +721,13 @@ __global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int d
                 }
             }
             __syncthreads();
-            for (int k = w; k < cnt; k += 4) {
+            for (int k = w; k < cnt; k += WPB) {
                 const double r1 = st_r[k], x = z - st_z[k];
                 const bool use = active && !(r == r1 && x == 0.0);
                 pair_accum<NMB, MODE>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, st_S + k * NMB, A, lg);
             }
         }
-        reduce_waves<NMB, MODE>(A, lds, nmodes);
+        reduce_waves<NMB, MODE, WPB>(A, lds);
         if (w == 0 && active) {
 #pragma unroll
             for (int n = 0; n < NMB; ++n) {
@@ -855,17 +756,30 @@ __global__ __launch_bounds__(256) void k_leaf(int M, int nmodes, int nrhs, int d
     }
 }
 
+template <int NMB, int MODE>
+__global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
+    int M, int nmodes, int nrhs, int depth, double rlo, double zlo, double invh, double chistar,
+    const int4 *__restrict__ chunks, SideView tv, SideView sv, const double *__restrict__ sinv,
+    const double2 *__restrict__ Sg, const double2 *__restrict__ loc, double2 *__restrict__ phi,
+    double2 *__restrict__ dphr, double2 *__restrict__ dphz, const double2 *__restrict__ Sdot,
+    double *__restrict__ gr, double *__restrict__ gz, int64_t ntot, int Cs)
+{
+    leaf_body<NMB, MODE>(M, nmodes, nrhs, depth, rlo, zlo, invh, chistar, chunks, tv, sv, sinv, Sg, loc, phi, dphr,
+                         dphz, Sdot, gr, gz, ntot, Cs, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- direct
 // One block (four waves) per 64 targets; each wave takes every fourth source.
 template <int NMB>
-__global__ __launch_bounds__(256) void k_direct(int nmodes, int nrhs, double chistar, SideView tv, int64_t nt,
+__global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_direct(int nmodes, int nrhs, double chistar, SideView tv, int64_t nt,
                                                SideView sv, const double *__restrict__ sinv, int64_t ns,
                                                const double2 *__restrict__ Sg, double2 *__restrict__ phi, int Cs)
 {
+    constexpr int WPB = PairShape<NMB>::WPB, ST = PairShape<NMB>::ST;
     extern __shared__ double lds[];
     double2 *st_S = reinterpret_cast<double2 *>(lds + leaf_lds_doubles<NMB, 0>());
-    double *st_r = reinterpret_cast<double *>(st_S + 64 * NMB);
-    double *st_z = st_r + 64, *st_i = st_z + 64;
+    double *st_r = reinterpret_cast<double *>(st_S + ST * NMB);
+    double *st_z = st_r + ST, *st_i = st_z + ST;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t tg = blockIdx.x * (int64_t)64 + lane;
     const bool active = tg < nt;
@@ -877,10 +791,10 @@ __global__ __launch_bounds__(256) void k_direct(int nmodes, int nrhs, double chi
     for (int q = 0; q < nrhs; ++q) {
         Acc<NMB, 0> A;
         A.zero();
-        for (int64_t tile = 0; tile < ns; tile += 64) {
+        for (int64_t tile = 0; tile < ns; tile += ST) {
             __syncthreads();
-            const int cnt = (int)min((int64_t)64, ns - tile);
-            for (int e = threadIdx.x; e < cnt * NMB; e += 256) {
+            const int cnt = (int)min((int64_t)ST, ns - tile);
+            for (int e = threadIdx.x; e < cnt * NMB; e += 64 * WPB) {
                 const int k = e / NMB, n = e - k * NMB;
                 const int64_t s = tile + k;
                 st_S[k * NMB + n] = Sg[s * Cs + n * nrhs + q];
@@ -891,13 +805,13 @@ __global__ __launch_bounds__(256) void k_direct(int nmodes, int nrhs, double chi
                 }
             }
             __syncthreads();
-            for (int k = w; k < cnt; k += 4) {
+            for (int k = w; k < cnt; k += WPB) {
                 const double r1 = st_r[k], x = z - st_z[k];
                 const bool use = active && !(r == r1 && x == 0.0);
                 pair_accum<NMB, 0>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, st_S + k * NMB, A, lg);
             }
         }
-        reduce_waves<NMB, 0>(A, lds, nmodes);
+        reduce_waves<NMB, 0, WPB>(A, lds);
         if (w == 0 && active) {
             const int orig = tv.perm[t];
 #pragma unroll
@@ -956,7 +870,7 @@ void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut 
         attr[pl.device & 63] = true;
     }
     if (tgt.nchunks == 0) return;
-    k_leaf<NMB, MODE><<<tgt.nchunks, 256, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
+    k_leaf<NMB, MODE><<<tgt.nchunks, 64 * PairShape<NMB>::WPB, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
                                                      pl.chistar, tgt.chunks, tv, sv, src.rinv, pl.Sg, loc,
                                                      (double2 *)out.phi, (double2 *)out.dr, (double2 *)out.dz,
                                                      (const double2 *)out.Sdot, out.gr, out.gz, tgt.n,
@@ -983,8 +897,104 @@ void launch_direct(Plan &pl, const Side &src, const Side &tgt, const EvalOut &ou
                                     (int)shm));
         attr[pl.device & 63] = true;
     }
-    k_direct<NMB><<<g, 256, shm, st>>>(pl.nmodes, pl.nrhs, pl.chistar, tv, tgt.n, sv, src.rinv, src.n, pl.Sg,
+    k_direct<NMB><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(pl.nmodes, pl.nrhs, pl.chistar, tv, tgt.n, sv, src.rinv, src.n, pl.Sg,
                                        (double2 *)out.phi, NMB * pl.nrhs);
+}
+
+// ------------------------------------------------------------- batches
+// Persistent kernels: each block walks the merged queue of (problem, item)
+// pairs of all problems of a batch, reading the problem's descriptor.
+constexpr int kPersistBlocks = 2048;
+
+__global__ __launch_bounds__(256) void kb_gather(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n,
+                                                int nmodes)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        const int64_t e = (int64_t)it.y * 256 + threadIdx.x;
+        if (e >= pd.ns * pd.Cs) continue;
+        const int64_t pp = e / pd.Cs;
+        const int c = (int)(e - pp * pd.Cs);
+        const int nn = c / pd.nrhs, qq = c - nn * pd.nrhs;
+        pd.Sg[e] = nn < nmodes ? pd.S[((int64_t)qq * nmodes + nn) * pd.ns + pd.sv.perm[pp]] : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_p2m(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        __syncthreads();
+        p2m_body(M, pd.C, pd.Cs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, pd.sv, pd.sbox[pd.d], pd.Sg,
+                 pd.mom[pd.d], it.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
+                                             int t)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        const int l = pd.d - t;
+        __syncthreads();
+        m2m_body(M, pd.C, l, pd.sbox[l], pd.sslot[l + 1], pd.mom[l + 1], pd.mom[l], it.y);
+    }
+}
+
+template <int LB, int TB>
+__global__ __launch_bounds__(64) void kb_s2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
+                                            int nmodes, int TS, int l)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        __syncthreads();
+        s2l_tile_body<LB, TB>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l],
+                              l > 2 ? pd.tslot[l - 1] : nullptr, l > 2 ? pd.loc[l - 1] : nullptr, pd.sslot[l],
+                              pd.mom[l], pd.tab[l], pd.loc[l], it.y);
+    }
+}
+
+template <int NMB>
+__global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDev *__restrict__ P,
+                                                                    const int2 *__restrict__ q, int n, int M,
+                                                                    int nmodes, double chistar)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        __syncthreads();
+        leaf_body<NMB, 0>(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, chistar,
+                          pd.chunks, pd.tv, pd.sv, pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr, nullptr, nullptr,
+                          nullptr, nullptr, pd.nf, pd.Cs, it.y);
+    }
+}
+
+template <int LB, int TB>
+void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
+{
+    const int P = (bq.M + 1) * (bq.M + 2) / 2;
+    size_t shm = sizeof(double2) * (size_t)TB * P;
+    int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
+    kb_s2l<LB, TB><<<g, 64, shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
+}
+
+template <int NMB>
+void launch_leaf_batch(const BatchQueues &bq, hipStream_t st)
+{
+    constexpr size_t shm = leaf_lds_bytes<NMB, 0>();
+    static bool attr[64] = {};
+    int dev = 0;
+    AXF_HIP(hipGetDevice(&dev));
+    if (shm > 65536 && !attr[dev & 63]) {
+        AXF_HIP(hipFuncSetAttribute((const void *)kb_leaf<NMB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        attr[dev & 63] = true;
+    }
+    int g = std::min(bq.nleaf, kPersistBlocks);
+    kb_leaf<NMB><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes, bq.chistar);
 }
 
 #define AXF_BUCKETS(X) X(4) X(9) X(12) X(17) X(24) X(33) X(48) X(64)
@@ -1053,6 +1063,70 @@ void run_direct(Plan &pl, const Side &src, const Side &tgt, const double *S, con
     }
     AXF_BUCKETS(AXF_DIR)
 #undef AXF_DIR
+}
+
+void run_batch(const BatchQueues &bq, hipStream_t st)
+{
+    if (bq.ngather)
+        kb_gather<<<std::min(bq.ngather, kPersistBlocks), 256, 0, st>>>(bq.probs, bq.gather, bq.ngather, bq.nmodes);
+    if (bq.np2m) kb_p2m<<<std::min(bq.np2m, kPersistBlocks), 256, 0, st>>>(bq.probs, bq.p2m, bq.np2m, bq.M);
+    for (int t = 1; t <= bq.maxd - 2; ++t)
+        if (bq.nm2m[t])
+            kb_m2m<<<std::min(bq.nm2m[t], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.m2m[t], bq.nm2m[t], bq.M, t);
+    for (int l = 2; l <= bq.maxd; ++l) {
+        if (!bq.ns2l[l]) continue;
+        switch (s2l_lb(bq.M)) {
+        case 1: launch_s2l_batch<1, 8>(bq, l, st); break;
+        case 2: launch_s2l_batch<2, 8>(bq, l, st); break;
+        case 3: launch_s2l_batch<3, 8>(bq, l, st); break;
+        case 4: launch_s2l_batch<4, 4>(bq, l, st); break;
+        case 5: launch_s2l_batch<5, 4>(bq, l, st); break;
+        case 6: launch_s2l_batch<6, 4>(bq, l, st); break;
+        case 7: launch_s2l_batch<7, 4>(bq, l, st); break;
+        default: launch_s2l_batch<8, 4>(bq, l, st); break;
+        }
+    }
+    if (bq.nleaf) {
+#define AXF_LEAFB(B)                          \
+    if (bq.nmb == B) {                        \
+        launch_leaf_batch<B>(bq, st);         \
+    }
+        AXF_BUCKETS(AXF_LEAFB)
+#undef AXF_LEAFB
+    }
+    AXF_HIP(hipGetLastError());
+}
+
+void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd)
+{
+    pd = ProbDev();
+    pd.d = pl.d;
+    pd.nrhs = pl.nrhs;
+    pd.C = pl.C;
+    pd.Cs = pl.Cs;
+    pd.rlo = pl.rlo;
+    pd.zlo = pl.zlo;
+    pd.invL = pl.invL;
+    pd.ns = pl.src.n;
+    pd.nf = pl.fld.n;
+    pd.sv = view_of(pl.src);
+    pd.tv = view_of(pl.fld);
+    pd.srinv = pl.src.rinv;
+    pd.S = (const double2 *)S;
+    pd.phi = (double2 *)phi;
+    pd.Sg = pl.Sg;
+    for (int l = 2; l <= pl.d; ++l) {
+        pd.sbox[l] = pl.src.box[l];
+        pd.sslot[l] = pl.src.slot[l];
+        pd.tbox[l] = pl.fld.box[l];
+        pd.tslot[l] = pl.fld.slot[l];
+        pd.tiles[l] = pl.fld.tiles[l];
+        pd.tile_slots[l] = pl.fld.tile_slots[l];
+        pd.mom[l] = pl.lev[l].mom;
+        pd.loc[l] = pl.lev[l].loc;
+        pd.tab[l] = pl.lev[l].tab;
+    }
+    pd.chunks = pl.fld.chunks;
 }
 
 }  // namespace axf

@@ -70,6 +70,12 @@ struct Sizer {
     }
 };
 
+// Device-side view of a sorted point set.
+struct SideView {
+    const double *r, *z;
+    const int32_t *perm, *off;
+};
+
 // ------------------------------------------------------------------ plan
 // One point set (the sources, or the field points) sorted onto the common
 // tree.  Box ids at a level are station-major: b = ir * 2^l + iz.
@@ -183,5 +189,41 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
              hipStream_t st);
 void run_direct(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out,
                 hipStream_t st);
+
+// ----------------------------------------------------------------- batches
+// Device descriptor of one problem of a batch: the pointers and scalars of
+// its plan that the persistent batch kernels read.
+struct ProbDev {
+    int d = 2, nrhs = 1, C = 1, Cs = 4;
+    double rlo = 0, zlo = 0, invL = 1;
+    int64_t ns = 0, nf = 0;
+    SideView sv{}, tv{};
+    const double *srinv = nullptr;
+    const double2 *S = nullptr;     // caller strengths [nrhs][nmodes][ns]
+    double2 *phi = nullptr;         // caller potential [nrhs][nmodes][nf]
+    double2 *Sg = nullptr;
+    const int32_t *sbox[AXF_MAX_DEPTH + 1] = {}, *sslot[AXF_MAX_DEPTH + 1] = {};
+    const int32_t *tbox[AXF_MAX_DEPTH + 1] = {}, *tslot[AXF_MAX_DEPTH + 1] = {};
+    const int4 *tiles[AXF_MAX_DEPTH + 1] = {};
+    const int32_t *tile_slots[AXF_MAX_DEPTH + 1] = {};
+    double2 *mom[AXF_MAX_DEPTH + 1] = {}, *loc[AXF_MAX_DEPTH + 1] = {};
+    const double *tab[AXF_MAX_DEPTH + 1] = {};
+    const int4 *chunks = nullptr;
+};
+
+// Merged work queues of a batch: one (problem, item) list per pass.
+// m2m[t] holds the step from level d-t+1 to d-t of each problem (so the
+// problems' different depths line up), s2l[l] the tiles x channels of level l.
+struct BatchQueues {
+    const ProbDev *probs = nullptr;
+    int2 *gather = nullptr, *p2m = nullptr, *leaf = nullptr;
+    int ngather = 0, np2m = 0, nleaf = 0;
+    int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *s2l[AXF_MAX_DEPTH + 1] = {};
+    int nm2m[AXF_MAX_DEPTH + 1] = {}, ns2l[AXF_MAX_DEPTH + 1] = {};
+    int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2;
+    double chistar = 1e300;
+};
+void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd);
+void run_batch(const BatchQueues &bq, hipStream_t st);
 
 }  // namespace axf

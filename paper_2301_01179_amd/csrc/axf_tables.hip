@@ -27,150 +27,270 @@ struct GeomDesc {
     double rout, rin, x, invh;   // box units; invh = 1 / h
 };
 
-// G^(n)(r, r1, x), n = 0..N, one thread: AGM start values, forward recursion
-// for chi < chistar, otherwise backward recursion on ratios normalised by G^(0).
-__device__ void green_scalar(int N, double r, double r1, double x, double chistar, double *G)
+// ------------------------------------------------------- double-double
+// The starting columns are built from sums and differences of neighbouring
+// modes, g^n +- g^(n-1).  Where n x / r is small (boxes far from the axis
+// relative to their separation) the modes agree to many digits and the
+// x recurrence amplifies rounding by up to ~1e14 at order 48, so G^(n), the
+// rational-factor coefficients and the starting recurrences run in
+// double-double arithmetic (an unevaluated sum hi + lo, ~106 bits): the
+// error-free transformations TwoSum (Knuth) and TwoProduct via fma, with
+// the accurate addition of Hida, Li and Bailey's double-double library.
+// The Laplace recursion that fills the rest of a table is well conditioned
+// and runs in FP64.
+//
+// The error terms are exact only if every product and sum is rounded on
+// its own: floating-point contraction (fusing a*b + c into one fma across
+// statements) is switched off for this file, and fma is written out where
+// it is meant.
+#pragma clang fp contract(off)
+struct dd {
+    double hi, lo;
+};
+
+__host__ __device__ __forceinline__ dd dd_two_sum(double a, double b)
 {
-    double dr = r - r1, sr = r + r1;
-    double rm2 = dr * dr + x * x, rp2 = sr * sr + x * x;
-    double rr = r * r1;
-    double rp = sqrt(rp2), rm = sqrt(rm2);
-    double a = rp, b = rm, c = 2.0 * rr / (rp + rm), csum = c * c, w = 1.0;
-    for (int it = 0; it < 48; ++it) {
-        double an = 0.5 * (a + b);
-        b = sqrt(a * b);
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__host__ __device__ __forceinline__ dd dd_fast_sum(double a, double b)   // |a| >= |b|
+{
+    double s = a + b;
+    return {s, b - (s - a)};
+}
+__host__ __device__ __forceinline__ dd dd_d(double a) { return {a, 0.0}; }
+__host__ __device__ __forceinline__ dd dd_prod(double a, double b)
+{
+    double p = a * b;
+    return {p, fma(a, b, -p)};
+}
+__host__ __device__ __forceinline__ dd operator+(dd a, dd b)
+{
+    dd s = dd_two_sum(a.hi, b.hi), t = dd_two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = dd_fast_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return dd_fast_sum(s.hi, s.lo);
+}
+__host__ __device__ __forceinline__ dd operator-(dd a) { return {-a.hi, -a.lo}; }
+__host__ __device__ __forceinline__ dd operator-(dd a, dd b) { return a + (-b); }
+__host__ __device__ __forceinline__ dd operator*(dd a, dd b)
+{
+    dd p = dd_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return dd_fast_sum(p.hi, p.lo);
+}
+__host__ __device__ __forceinline__ dd operator*(dd a, double b)
+{
+    dd p = dd_prod(a.hi, b);
+    p.lo = fma(a.lo, b, p.lo);
+    return dd_fast_sum(p.hi, p.lo);
+}
+__host__ __device__ __forceinline__ dd operator/(dd a, dd b)
+{
+    double q1 = a.hi / b.hi;
+    dd r = a - b * q1;
+    double q2 = r.hi / b.hi;
+    r = r - b * q2;
+    double q3 = r.hi / b.hi;
+    dd q = dd_fast_sum(q1, q2);
+    return q + dd_d(q3);
+}
+__host__ __device__ __forceinline__ dd dd_sqrt(dd a)
+{
+    if (a.hi <= 0.0) return dd_d(0.0);
+    double x = sqrt(a.hi);
+    dd x2 = dd_prod(x, x);
+    double corr = ((a - x2).hi) / (2.0 * x);
+    return dd_fast_sum(x, corr);
+}
+__device__ __forceinline__ dd dd_shfl_xor(dd a, int m) { return {__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)}; }
+
+// Threads of k_tab_start; a mode's partial sums are split over LPM lanes.
+constexpr int kStartThreads = 512;
+__host__ __device__ inline int start_lpm(int nw1)
+{
+    int l = 16;
+    while (l > 1 && l * nw1 > kStartThreads) l >>= 1;
+    return l;
+}
+
+// G^(n)(r, r1, x), n = 0..N, in double-double (one thread): the AGM gives
+// G^(0) = 1 / (2 AGM(rho+, rho-)) and G^(1) / G^(0) = sum_n 2^(n-1) c_n^2 / (2 r r1);
+// forward recursion in n below chistar, otherwise backward recursion on the
+// ratios G^(n) / G^(n-1) started far enough up for double-double accuracy.
+__host__ __device__ void green_dd(int N, double r, double r1, double x, double chistar, dd *G, int stride)
+{
+    dd sr = dd_two_sum(r, r1), df = dd_two_sum(r, -r1), xx = dd_prod(x, x);
+    dd rp2 = sr * sr + xx, rm2 = df * df + xx, rr = dd_prod(r, r1);
+    dd a = dd_sqrt(rp2), b = dd_sqrt(rm2);
+    dd c = (rr * 2.0) / (a + b);
+    dd csum = c * c;
+    double w = 1.0;
+    for (int it = 0; it < 64; ++it) {
+        dd an = (a + b) * 0.5;
+        b = dd_sqrt(a * b);
         a = an;
-        if (c <= 0x1p-30 * a) break;
-        c = 0.5 * (a - b);
+        c = (c * c) / ((a + b) * 2.0);   // c_(n+1) = c_n^2 / (4 a_(n+1))
         w *= 2.0;
-        csum = fma(w * c, c, csum);
+        dd t = c * c * w;
+        csum = csum + t;
+        if (c.hi <= 0x1p-108 * a.hi) break;   // a is within c of the AGM
     }
-    double g0 = 0.5 / a;
+    dd g0 = dd_d(0.5) / a;
     G[0] = g0;
     if (N < 1) return;
-    double chi = (rp2 + rm2) / (4.0 * rr);
-    if (chi < chistar) {
-        G[1] = g0 * csum / (2.0 * rr);
+    dd chi = (rp2 + rm2) / (rr * 4.0);
+    if (chi.hi < chistar) {
+        G[stride] = g0 * csum / (rr * 2.0);
         for (int n = 1; n < N; ++n)
-            G[n + 1] = (4.0 * n * chi * G[n] - (2.0 * n - 1.0) * G[n - 1]) / (2.0 * n + 1.0);
+            G[(n + 1) * stride] = (chi * G[n * stride] * (4.0 * n) - G[(n - 1) * stride] * (2.0 * n - 1.0)) /
+                                  dd_d(2.0 * n + 1.0);
     } else {
-        double dchi = rm2 / (2.0 * rr);
-        int ntop = N + 10 + (int)ceil(20.0 / sqrt(2.0 * dchi));
-        if (ntop > kMillerMax) ntop = kMillerMax;
-        // t = G^(n) / G^(n-1) for n = ntop .. 1
-        double t = 0.0;
+        double dchi = (rm2 / (rr * 2.0)).hi;
+        int ntop = N + 10 + (int)ceil(40.0 / sqrt(2.0 * dchi));
+        dd t = dd_d(0.0);
         for (int n = ntop; n >= 1; --n) {
-            t = (2.0 * n - 1.0) / (4.0 * n * chi - (2.0 * n + 1.0) * t);
-            if (n <= N) G[n] = t;   // ratio, turned into values below
+            t = dd_d(2.0 * n - 1.0) / (chi * (4.0 * n) - t * (2.0 * n + 1.0));
+            if (n <= N) G[n * stride] = t;
         }
-        for (int n = 1; n <= N; ++n) G[n] *= G[n - 1];
+        for (int n = 1; n <= N; ++n) G[n * stride] = G[n * stride] * G[(n - 1) * stride];
     }
 }
 
-constexpr int kStartThreads = 128;   // >= AXF_MAX_MODES + 1
+// Sum over the LPM lanes of a mode (lanes of one mode are adjacent and
+// inside one wave).
+__device__ __forceinline__ dd lane_reduce(dd s, int lpm)
+{
+    for (int m = 1; m < lpm; m <<= 1) s = s + dd_shfl_xor(s, m);
+    return s;
+}
 
 // Starting columns g_{0,0,k}, g_{1,0,k}, g_{0,1,k}, g_{1,1,k} for all modes of
-// one geometry; out layout [geom][n][4][2M+1].
+// one geometry; out layout [geom][n][4][2M+1].  Coefficients (1/q!) d^q/dx^q
+// of the rational factors: x/rho^2 = (-1)^q Re w^-(q+1) and the companions
+// below come from 1/rho^2 = sum u_q t^q, whose coefficients obey the
+// three-term recurrence that multiplying by rho^2(x + t) gives.
 __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, double chistar,
                                                             const GeomDesc *__restrict__ geoms,
                                                             double *__restrict__ out)
 {
-    extern __shared__ double sm[];
+    extern __shared__ dd smd[];
     const int K = 2 * M;
     const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;   // g^(-1) = g^(1) needs mode 1
-    const int L = K + 2;
-    double *fp = sm, *fm = fp + L, *pp = fm + L, *pm = pp + L, *qp = pm + L, *qm = qp + L;
-    double *dp = qm + L, *dm = dp + L;
-    double *g00 = dm + L;                      // [Nw+1][L]
-    double *g01 = g00 + (Nw + 1) * L;
-    double *g10 = g01 + (Nw + 1) * L;
-    double *g11 = g10 + (Nw + 1) * L;
+    const int L = K + 1;
+    dd *up = smd, *um = up + L, *fp = um + L, *fm = fp + L, *pp = fm + L, *pm = pp + L, *qp = pm + L,
+       *qm = qp + L, *dp = qm + L, *dm = dp + L;
+    dd *g00 = dm + L;                 // [Nw+1][L]
+    dd *g01 = g00 + (Nw + 1) * L;     // [Nw+1][L]
     const GeomDesc gd = geoms[blockIdx.x];
     const double r = gd.rout, r1 = gd.rin, x = gd.x;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        double G[AXF_MAX_MODES + 1];
-        green_scalar(Nw, r, r1, x, chistar, G);
-        for (int n = 0; n <= Nw; ++n) g00[n * L] = G[n];
-        // (1/q!) d^q/dx^q of x/rho^2 = (-1)^q Re w^-(q+1),
-        // (r^2 - r1^2 - x^2)/rho^2 = -1 + 2 r Im w^-1, its r1-derivative
-        // +-2 r Re w^-2 (+ for rho+, - for rho-), w = x - i (r +- r1).
+    const int tid = threadIdx.x;
+    const int lpm = start_lpm(Nw + 1);
+    const int n = tid / lpm, j = tid - n * lpm;      // mode and lane within the mode
+    const bool active = n <= Nw;
+    const int nm = n == 0 ? 1 : n - 1;
+    double *o = out + (size_t)blockIdx.x * nmodes * 4 * L;
+    if (tid == 0) green_dd(Nw, r, r1, x, chistar, g00, L);
+    if (tid == 64 || (tid == 0 && blockDim.x <= 64)) {
         for (int sgn = 0; sgn < 2; ++sgn) {
-            double cc = sgn == 0 ? r + r1 : r - r1;
-            double den = x * x + cc * cc;
-            double ire = x / den, iim = cc / den;   // 1/w
-            double pre = ire, pim = iim;            // running w^-(q+1)
-            double *f = sgn == 0 ? fp : fm, *p = sgn == 0 ? pp : pm, *q = sgn == 0 ? qp : qm;
-            double *dd = sgn == 0 ? dp : dm;
-            double wre = 0, wim = 0;                // w^-(q+2)
-            wre = pre * ire - pim * iim;
-            wim = pre * iim + pim * ire;
-            for (int k = 0; k <= K; ++k) {
-                double s = (k & 1) ? -1.0 : 1.0;
-                f[k] = s * pre;
-                p[k] = (k == 0 ? -1.0 : 0.0) + 2.0 * r * s * pim;
-                // r <-> r1 exchange: c+ unchanged, c- -> -c- (conjugates w-)
-                q[k] = (k == 0 ? -1.0 : 0.0) + (sgn == 0 ? 2.0 : -2.0) * r1 * s * pim;
-                dd[k] = (sgn == 0 ? 2.0 : -2.0) * r * s * (k + 1.0) * wre;
-                double nre = pre * ire - pim * iim, nim = pre * iim + pim * ire;
-                pre = nre;
-                pim = nim;
-                double mre = wre * ire - wim * iim, mim = wre * iim + wim * ire;
-                wre = mre;
-                wim = mim;
-            }
+            dd cc = sgn == 0 ? dd_two_sum(r, r1) : dd_two_sum(r, -r1);
+            dd rho2 = cc * cc + dd_prod(x, x);
+            dd *u = sgn == 0 ? up : um;
+            u[0] = dd_d(1.0) / rho2;
+            if (K >= 1) u[1] = -(u[0] * (2.0 * x)) / rho2;
+            for (int q = 2; q <= K; ++q) u[q] = -(u[q - 1] * (2.0 * x) + u[q - 2]) / rho2;
         }
     }
     __syncthreads();
+    const dd A0 = dd_prod(r, r) - dd_prod(r1, r1) - dd_prod(x, x);
+    const dd B0 = dd_prod(r1, r1) - dd_prod(r, r) - dd_prod(x, x);
+    for (int q = tid; q <= K; q += blockDim.x) {
+        dd u1p = q >= 1 ? up[q - 1] : dd_d(0.0), u2p = q >= 2 ? up[q - 2] : dd_d(0.0);
+        dd u1m = q >= 1 ? um[q - 1] : dd_d(0.0), u2m = q >= 2 ? um[q - 2] : dd_d(0.0);
+        fp[q] = up[q] * x + u1p;
+        fm[q] = um[q] * x + u1m;
+        pp[q] = A0 * up[q] - u1p * (2.0 * x) - u2p;
+        pm[q] = A0 * um[q] - u1m * (2.0 * x) - u2m;
+        qp[q] = B0 * up[q] - u1p * (2.0 * x) - u2p;
+        qm[q] = B0 * um[q] - u1m * (2.0 * x) - u2m;
+    }
+    __syncthreads();
+    // d/dr1 of p = (r^2 - r1^2 - x^2) / rho^2: -2 r1 / rho^2 - p (d rho^2 / dr1) / rho^2
+    for (int q = tid; q <= K; q += blockDim.x) {
+        dd cpu = dd_d(0.0), cmu = dd_d(0.0);
+        for (int s2 = 0; s2 <= q; ++s2) {
+            cpu = cpu + pp[s2] * up[q - s2];
+            cmu = cmu + pm[s2] * um[q - s2];
+        }
+        dp[q] = up[q] * (-2.0 * r1) - cpu * dd_two_sum(r, r1) * 2.0;
+        dm[q] = um[q] * (-2.0 * r1) + cmu * dd_two_sum(r, -r1) * 2.0;
+    }
     // x-derivatives, k-outer, n-inner (eq. gfunc:derivatives:x)
     for (int k = 0; k < K; ++k) {
-        if (t <= Nw) {
-            int nm = t == 0 ? 1 : t - 1;
-            double s = 0.0;
-            for (int q = 0; q <= k; ++q) {
-                double a = g00[t * L + k - q], b = g00[nm * L + k - q];
-                s += (a + b) * fp[q] + (a - b) * fm[q];
+        dd s = dd_d(0.0);
+        if (active)
+            for (int q = j; q <= k; q += lpm) {
+                dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
+                s = s + (a + b) * fp[q] + (a - b) * fm[q];
             }
-            g00[t * L + k + 1] = (t - 0.5) * s / (k + 1.0);
-        }
+        s = lane_reduce(s, lpm);
+        if (active && j == 0) g00[n * L + k + 1] = (s * (n - 0.5)) / dd_d(k + 1.0);
         __syncthreads();
     }
+    // r-derivative and its r <-> r1 image: g10 goes out, g01 stays for g11
     if (M >= 1) {
-        if (t <= Nw) {
-            int nm = t == 0 ? 1 : t - 1;
-            for (int k = 0; k <= K - 1; ++k) {
-                double s1 = 0.0, s2 = 0.0;
-                for (int q = 0; q <= k; ++q) {
-                    double a = g00[t * L + k - q], b = g00[nm * L + k - q];
-                    s1 += (a + b) * pp[q] + (a - b) * pm[q];
-                    s2 += (a + b) * qp[q] + (a - b) * qm[q];
+        for (int k = 0; k <= K - 1; ++k) {
+            dd s1 = dd_d(0.0), s2 = dd_d(0.0);
+            if (active)
+                for (int q = j; q <= k; q += lpm) {
+                    dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
+                    dd sp = a + b, sm = a - b;
+                    s1 = s1 + sp * pp[q] + sm * pm[q];
+                    s2 = s2 + sp * qp[q] + sm * qm[q];
                 }
-                double g = g00[t * L + k];
-                g10[t * L + k] = (-g + (t - 0.5) * s1) / (2.0 * r);
-                g01[t * L + k] = (-g + (t - 0.5) * s2) / (2.0 * r1);
+            s1 = lane_reduce(s1, lpm);
+            s2 = lane_reduce(s2, lpm);
+            if (active && j == 0) {
+                dd g = g00[n * L + k];
+                dd v10 = (s1 * (n - 0.5) - g) / dd_d(2.0 * r);
+                dd v01 = (s2 * (n - 0.5) - g) / dd_d(2.0 * r1);
+                g01[n * L + k] = v01;
+                if (n < nmodes) o[((size_t)n * 4 + 1) * L + k] = v10.hi;
             }
         }
         __syncthreads();
-        if (t <= Nw) {
-            int nm = t == 0 ? 1 : t - 1;
-            for (int k = 0; k <= K - 2; ++k) {
-                double s = 0.0;
-                for (int q = 0; q <= k; ++q) {
-                    double a = g00[t * L + k - q], b = g00[nm * L + k - q];
-                    double e = g01[t * L + k - q], f = g01[nm * L + k - q];
-                    s += (a + b) * dp[q] + (e + f) * pp[q] + (a - b) * dm[q] + (e - f) * pm[q];
+        for (int k = 0; k <= K - 2; ++k) {
+            dd s = dd_d(0.0);
+            if (active)
+                for (int q = j; q <= k; q += lpm) {
+                    dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
+                    dd e = g01[n * L + k - q], f = g01[nm * L + k - q];
+                    s = s + (a + b) * dp[q] + (e + f) * pp[q] + (a - b) * dm[q] + (e - f) * pm[q];
                 }
-                g11[t * L + k] = (-g01[t * L + k] + (t - 0.5) * s) / (2.0 * r);
-            }
+            s = lane_reduce(s, lpm);
+            if (active && j == 0 && n < nmodes)
+                o[((size_t)n * 4 + 3) * L + k] = ((s * (n - 0.5) - g01[n * L + k]) / dd_d(2.0 * r)).hi;
         }
-        __syncthreads();
     }
-    for (int e = t; e < nmodes * 4 * (K + 1); e += blockDim.x) {
-        int n = e / (4 * (K + 1)), rem = e - n * 4 * (K + 1), col = rem / (K + 1), k = rem - col * (K + 1);
-        const double *src = col == 0 ? g00 : col == 1 ? g10 : col == 2 ? g01 : g11;
-        bool ok = (col == 0) || (col < 3 && k <= K - 1) || (col == 3 && k <= K - 2);
-        out[(size_t)blockIdx.x * nmodes * 4 * (K + 1) + e] = (ok && M >= (col == 0 ? 0 : 1)) ? src[n * L + k] : 0.0;
+    // g00, g01 and the zero tails
+    for (int e = tid; e < nmodes * 4 * L; e += blockDim.x) {
+        int nn = e / (4 * L), rem = e - nn * 4 * L, col = rem / L, k = rem - col * L;
+        if (col == 0) {
+            o[e] = g00[nn * L + k].hi;
+        } else if (col == 2) {
+            o[e] = (M >= 1 && k <= K - 1) ? g01[nn * L + k].hi : 0.0;
+        } else if (M < 1 || (col == 1 && k > K - 1) || (col == 3 && k > K - 2)) {
+            o[e] = 0.0;
+        }
     }
+}
+
+size_t start_lds_bytes(int M, int nmodes)
+{
+    const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;
+    return sizeof(dd) * (size_t)(2 * M + 1) * (10 + 2 * (Nw + 1));
 }
 
 // Laplace recursion for one (geometry, mode) in LDS; writes the scaled table.
@@ -290,16 +410,14 @@ void build_tables(Plan &pl, hipStream_t st)
     GeomDesc *dgeo = reinterpret_cast<GeomDesc *>(pl.tab_scratch);
     double *dstart = reinterpret_cast<double *>(pl.tab_scratch) + 4 * (size_t)ng;
     AXF_HIP(hipMemcpyAsync(dgeo, geoms.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
-    const int Nw = nm - 1 < 1 ? 1 : nm - 1;
-    size_t sm_start = sizeof(double) * ((size_t)8 * (K + 2) + (size_t)4 * (Nw + 1) * (K + 2));
+    size_t sm_start = start_lds_bytes(M, nm);
     size_t sm_lap = sizeof(double) * TS;
     static bool attr_done[64] = {};
     if (!attr_done[pl.device & 63]) {
         AXF_HIP(hipFuncSetAttribute((const void *)k_tab_laplace, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     sizeof(double) * (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 1)));
         AXF_HIP(hipFuncSetAttribute((const void *)k_tab_start, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    sizeof(double) * (8 * (2 * AXF_MAX_ORDER + 2) +
-                                                      4 * (AXF_MAX_MODES + 1) * (2 * AXF_MAX_ORDER + 2))));
+                                    (int)start_lds_bytes(AXF_MAX_ORDER, AXF_MAX_MODES)));
         attr_done[pl.device & 63] = true;
     }
     k_tab_start<<<ng, kStartThreads, sm_start, st>>>(M, nm, pl.chistar, dgeo, dstart);

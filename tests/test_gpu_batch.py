@@ -1,0 +1,134 @@
+"""Batched evaluation on the GPU (marked gpu).
+
+  * a small batch of uneven problems (one ring, distinct source and field
+    sets, fixed and autotuned depths, 1..8 right-hand sides): the captured
+    graph against the oracle FMM of each problem at the depth the batch chose;
+  * graph replays with eager work in between (new strengths written in place
+    by torch), every replay checked against the plain per-problem launches;
+  * the 64-problem workload (sizes log-uniform in 1e3..2e5 rings of the
+    ring-box geometry, 1..8 right-hand sides, modes 0..16, M = 12): graph
+    against plain launches, sampled points against the oracle's per-point
+    FMM and the exact sum.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import gpu, need_gpu, rel_err, to_np
+from oracle import oracle as O
+from paper_2301_01179_amd import inputs
+
+TOL = 1e-12
+
+
+def _axf():
+    from paper_2301_01179_amd import axf
+    return axf
+
+
+def _small_problems(nmodes):
+    probs = []
+    spec = [(300, 1, 0), (1200, 3, 0), (1, 1, 0), (2500, 2, 4), (700, 8, 0), (60, 1, 3)]
+    for i, (n, q, depth) in enumerate(spec):
+        r, z, S = inputs.ring_box(n, nmodes, nrhs=q, seed=100 + i)
+        probs.append((r, z, r, z, S, depth))
+    # distinct source and field sets
+    rs, zs, rf, zf, S = inputs.annulus(900, 400, nmodes, nrhs=2, seed=7)
+    probs.append((rs, zs, rf, zf, S, 0))
+    return probs
+
+
+@gpu
+def test_batch_small_vs_oracle():
+    need_gpu()
+    axf = _axf()
+    nmodes, M = 5, 8
+    probs = _small_problems(nmodes)
+    b = axf.Batch(probs, nmodes, M)
+    depths = b.depths()
+    print("depths", depths)
+    assert depths[3] == 4 and depths[5] == 3
+    outs = [to_np(t) for t in b.launch()]
+    for (rs, zs, rf, zf, S, _), d, phi in zip(probs, depths, outs):
+        ref = O.fmm(rs, zs, rf, zf, S, M, d)
+        e = rel_err(phi, ref)
+        assert np.all(np.isfinite(phi))
+        assert e.max() < TOL, (d, e.max())
+    b.close()
+
+
+@gpu
+def test_batch_graph_replays_with_eager_work():
+    need_gpu()
+    axf = _axf()
+    nmodes, M = 5, 8
+    probs = _small_problems(nmodes)
+    b = axf.Batch(probs, nmodes, M)
+    rng = np.random.default_rng(3)
+    for rep in range(4):
+        for S in b.strengths:               # eager torch work between replays
+            new = rng.standard_normal(tuple(S.shape)) + 1j * rng.standard_normal(tuple(S.shape))
+            S.copy_(torch.from_numpy(new))
+        b.launch()
+        torch.cuda.synchronize()
+        graph = [to_np(t).copy() for t in b.outputs]
+        b.launch_plain()
+        torch.cuda.synchronize()
+        plain = [to_np(t) for t in b.outputs]
+        for g, p in zip(graph, plain):
+            assert rel_err(g, p).max() < 1e-14, rep
+        if rep == 2:
+            d = b.depths()[1]
+            pb = probs[1]
+            ref = O.fmm(pb[0], pb[1], pb[2], pb[3], to_np(b.strengths[1]), M, d)
+            assert rel_err(graph[1], ref).max() < TOL
+    b.close()
+
+
+@gpu
+def test_batch_64_problems():
+    need_gpu()
+    axf = _axf()
+    nmodes, M = 17, 12
+    sizes, nrhs = inputs.batched_sizes(64, 1e3, 2e5, seed=4)
+    probs = []
+    for i, (n, q) in enumerate(zip(sizes, nrhs)):
+        r, z, S = inputs.ring_box(int(n), nmodes, nrhs=int(q), seed=1000 + i)
+        probs.append((r, z, r, z, S))
+    b = axf.Batch(probs, nmodes, M)
+    depths = b.depths()
+    print("sizes", sizes.tolist(), "depths", depths, flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    graph = [to_np(t).copy() for t in b.outputs]
+    b.launch_plain()
+    torch.cuda.synchronize()
+    for i, t in enumerate(b.outputs):
+        assert rel_err(graph[i], to_np(t)).max() < 1e-14, i
+    rng = np.random.default_rng(17)
+    for i in (int(np.argmin(sizes)), int(np.argsort(sizes)[32]), int(np.argmax(sizes))):
+        r, z, _, _, S = probs[i]
+        idx = np.sort(rng.choice(r.size, 3, replace=False))
+        ref_pts = O.fmm_points(r, z, r, z, S, M, depths[i], idx)
+        e = (np.abs(graph[i][..., idx] - ref_pts).max(axis=-1) / np.abs(ref_pts).max(axis=-1)).max()
+        print("problem", i, "n", r.size, "depth", depths[i], "parity", e, flush=True)
+        assert e < TOL
+        samp = np.sort(rng.choice(r.size, 64, replace=False))
+        ref = O.direct(r, z, r[samp], z[samp], S)
+        eps = (np.abs(graph[i][..., samp] - ref).max(axis=-1) / np.abs(ref).max(axis=-1)).max()
+        print("eps vs direct", eps, flush=True)
+        assert eps < 5e-6
+    b.close()
+
+
+@gpu
+def test_batch_rejects_bad_arguments():
+    need_gpu()
+    axf = _axf()
+    r, z, S = inputs.ring_box(100, 3, seed=1)
+    with pytest.raises(ValueError):
+        axf.Batch([(r, z, r, z, S[:, :2])], 3, 4)
+    with pytest.raises(axf.AxfError):
+        axf.Batch([(r, z, r, z, S, 15)], 3, 4)       # depth beyond the maximum
+    with pytest.raises(axf.AxfError):
+        axf.Batch([(r, z, r, z, S)], 3, 30)          # order beyond the maximum

@@ -1,0 +1,132 @@
+"""Full-size workloads on the GPU, checked on sampled outputs (marked gpu).
+
+The oracle's per-point FMM (direct moments of every interaction-list box,
+no shifts) computes the FMM value at single field points of problems far too
+large for the full reference FMM; it equals Algorithm 1 to rounding (pinned
+in test_oracle_fmm).  Accuracy against the exact sum (eq. results:error) is
+measured with the oracle's direct sum at sampled points.
+
+  * annulus: 50,000 sources + 50,000 field points, modes 0..16, M = 12,
+    <= 64 points per leaf; and M = 24 at the same geometry (<= 1e-10);
+  * generator curve: 1,000,000 rings = field points, modes 0..32, M = 16;
+  * adjoint: 200,000 rings of the ring-box geometry, modes 0..16, M = 12.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import gpu, need_gpu, rel_err, to_np
+from oracle import oracle as O
+from paper_2301_01179_amd import inputs
+
+TOL_IMPL = 1e-12
+
+
+def _axf():
+    from paper_2301_01179_amd import axf
+    return axf
+
+
+def _sampled_eps(phi_s, ref_s):
+    return (np.abs(phi_s - ref_s).max(axis=-1) / np.abs(ref_s).max(axis=-1)).max()
+
+
+@gpu
+def test_annulus_50k_order12():
+    need_gpu()
+    axf = _axf()
+    rs, zs, rf, zf, S = inputs.annulus(50000, 50000, 17, 1, seed=2)
+    plan = axf.Plan(rs, zs, rf, zf, 17, 12, depth=0, max_leaf=64)
+    d = plan.info()["depth"]
+    print("depth", d)
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(50000, 48, replace=False))
+    ref_pts = O.fmm_points(rs, zs, rf, zf, S, 12, d, idx)
+    e = (np.abs(phi[..., idx] - ref_pts).max(axis=-1) / np.abs(ref_pts).max(axis=-1)).max()
+    print("implementation parity at 48 points", e)
+    assert e < TOL_IMPL
+    samp = np.sort(rng.choice(50000, 1000, replace=False))
+    ref = O.direct(rs, zs, rf[samp], zf[samp], S)
+    eps = _sampled_eps(phi[..., samp], ref)
+    print("eps vs direct", eps)
+    assert eps < 5e-6
+
+
+@gpu
+def test_annulus_50k_order24_meets_1e10():
+    need_gpu()
+    axf = _axf()
+    rs, zs, rf, zf, S = inputs.annulus(50000, 50000, 17, 1, seed=2)
+    plan = axf.Plan(rs, zs, rf, zf, 17, 24, depth=4)
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    rng = np.random.default_rng(12)
+    samp = np.sort(rng.choice(50000, 500, replace=False))
+    ref = O.direct(rs, zs, rf[samp], zf[samp], S)
+    eps = _sampled_eps(phi[..., samp], ref)
+    print("eps at M=24", eps)
+    assert eps <= 1e-10
+    idx = samp[:16]
+    ref_pts = O.fmm_points(rs, zs, rf, zf, S, 24, 4, idx)
+    assert _sampled_eps(phi[..., idx], ref_pts) < TOL_IMPL
+
+
+@gpu
+def test_generator_curve_1m():
+    need_gpu()
+    axf = _axf()
+    r, z, S = inputs.generator_curve(1_000_000, 33, 1, seed=3)
+    depth = 8
+    plan = axf.Plan(r, z, r, z, 33, 16, depth=depth)
+    info = plan.info()
+    print("levels", info["levels"], "near pairs", plan.work()["near_pairs"])
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    assert np.all(np.isfinite(phi))
+    rng = np.random.default_rng(13)
+    idx = np.sort(rng.choice(r.size, 6, replace=False))
+    ref_pts = O.fmm_points(r, z, r, z, S, 16, depth, idx)
+    e = _sampled_eps(phi[..., idx], ref_pts)
+    print("implementation parity at 6 points", e)
+    assert e < 1e-11
+    # accuracy against the exact sum at sampled field points (GPU direct
+    # at the sampled points, itself pinned to the oracle below)
+    samp = np.sort(rng.choice(r.size, 400, replace=False))
+    dplan = axf.Plan(r, z, r[samp], z[samp], 33, 0, depth=2)
+    dref = to_np(dplan.evaluate_direct(torch.from_numpy(S)))
+    ocheck = O.direct(r, z, r[samp[:8]], z[samp[:8]], S)
+    assert _sampled_eps(dref[..., :8], ocheck) < 1e-11
+    eps = _sampled_eps(phi[..., samp], dref)
+    print("eps vs direct at 400 points", eps)
+    assert eps < 1e-6
+
+
+@gpu
+def test_adjoint_200k():
+    need_gpu()
+    axf = _axf()
+    n = 200_000
+    r, z, S = inputs.ring_box(n, 17, 1, seed=5)
+    _, _, S_target = inputs.ring_box(n, 17, 1, seed=6)
+    plan = axf.Plan(r, z, r, z, 17, 12, depth=0, max_leaf=32)
+    d = plan.info()["depth"]
+    St = torch.from_numpy(S)
+    phi = plan.evaluate(St)
+    phi_t = plan.evaluate(torch.from_numpy(S_target))
+    gphi = 2 * (phi - phi_t)          # L = sum |phi - phi_target|^2
+    gS, gr, gz = plan.adjoint(gphi, St)
+    gS, gr, gz, gphi_np = to_np(gS), to_np(gr), to_np(gz), to_np(gphi)
+    rng = np.random.default_rng(14)
+    # implementation parity: the swapped FMM at sampled rings
+    idx = np.sort(rng.choice(n, 24, replace=False))
+    ref_pts = O.fmm_points(r, z, r, z, gphi_np, 12, d, idx)
+    e = _sampled_eps(gS[..., idx], ref_pts)
+    print("adjoint implementation parity", e)
+    assert e < TOL_IMPL
+    # accuracy against the oracle's direct adjoint at 300 sampled rings
+    samp = np.sort(rng.choice(n, 300, replace=False))
+    dS, dgr, dgz = O.direct_adjoint(r[samp], z[samp], r, z, S[..., samp], gphi_np)
+    eS = _sampled_eps(gS[..., samp], dS)
+    er = np.abs(gr[samp] - dgr).max() / np.abs(dgr).max()
+    ez = np.abs(gz[samp] - dgz).max() / np.abs(dgz).max()
+    print("vs oracle direct adjoint", eS, er, ez)
+    assert eS < 1e-5 and er < 1e-4 and ez < 1e-4

@@ -1,0 +1,152 @@
+"""Edge cases of the GPU library (marked gpu): invalid geometry, single and
+coincident points, padded mode counts, odd right-hand-side counts, the order,
+mode and depth limits, grid-aligned points and points near the axis, each
+checked against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import gpu, need_gpu, rel_err, to_np
+from oracle import oracle as O
+from paper_2301_01179_amd import inputs
+
+TOL = 1e-12
+
+
+def _axf():
+    from paper_2301_01179_amd import axf
+    return axf
+
+
+@gpu
+@pytest.mark.parametrize("bad", ["zero_r", "neg_r", "nan_z", "inf_r"])
+def test_invalid_geometry(bad):
+    need_gpu()
+    axf = _axf()
+    r, z, _ = inputs.ring_box(50, 3, seed=2)
+    r, z = r.copy(), z.copy()
+    if bad == "zero_r":
+        r[7] = 0.0
+    elif bad == "neg_r":
+        r[3] = -0.1
+    elif bad == "nan_z":
+        z[11] = np.nan
+    else:
+        r[0] = np.inf
+    with pytest.raises(axf.AxfError) as ei:
+        axf.Plan(r, z, r, z, 3, 4, depth=2)
+    assert ei.value.status == 2
+
+
+def _check(r, z, rf, zf, S, M, depth, tol=TOL):
+    axf = _axf()
+    nrhs, nm, _ = S.shape
+    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs)
+    d = plan.info()["depth"]
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    ref = O.fmm(r, z, rf, zf, S, M, d)
+    e = rel_err(phi, ref)
+    assert np.all(np.isfinite(phi))
+    assert e.max() < tol, e.max()
+    dphi = to_np(plan.evaluate_direct(torch.from_numpy(S)))
+    dref = O.direct(r, z, rf, zf, S)
+    assert rel_err(dphi, dref).max() < tol
+    return phi, ref
+
+
+@gpu
+def test_single_source_single_target():
+    need_gpu()
+    S = np.array([[[1.0 + 2.0j]], [[0.5 - 1j]]]).reshape(2, 1, 1)
+    _check(np.array([1.0]), np.array([0.0]), np.array([1.3]), np.array([0.2]), S, 4, 2)
+
+
+@gpu
+def test_all_points_coincide():
+    """Every source sits on the single field point: the potential is zero."""
+    need_gpu()
+    axf = _axf()
+    r = np.full(40, 0.8)
+    z = np.full(40, 0.1)
+    S = np.ones((1, 3, 40), dtype=np.complex128)
+    plan = axf.Plan(r, z, r[:1], z[:1], 3, 4, depth=2)
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    assert np.all(phi == 0)
+
+
+@gpu
+@pytest.mark.parametrize("nmodes,nrhs", [(1, 1), (5, 3), (13, 2), (2, 8)])
+def test_mode_padding_and_rhs(nmodes, nrhs):
+    need_gpu()
+    r, z, S = inputs.ring_box(500, nmodes, nrhs=nrhs, seed=nmodes + nrhs)
+    _check(r, z, r, z, S, 6, 3)
+
+
+@gpu
+@pytest.mark.parametrize("M", [0, 1, 2, 24])
+def test_order_limits(M):
+    need_gpu()
+    r, z, S = inputs.ring_box(300, 3, seed=40 + M)
+    _check(r, z, r, z, S, M, 3)
+
+
+@gpu
+def test_max_modes():
+    need_gpu()
+    r, z, S = inputs.ring_box(200, 64, seed=64)
+    _check(r, z, r, z, S, 5, 2, tol=1e-11)
+
+
+@gpu
+def test_deep_tree():
+    """Depth 9 on 1,200 points: many empty boxes, tiles of one box."""
+    need_gpu()
+    r, z, S = inputs.ring_box(1200, 3, seed=9)
+    _check(r, z, r, z, S, 4, 9)
+
+
+@gpu
+def test_grid_aligned_points():
+    """Points exactly on box boundaries must fall in the same boxes as in the
+    oracle (the same IEEE operations define the tree)."""
+    need_gpu()
+    g = np.arange(0, 17) / 16.0
+    R, Z = np.meshgrid(0.5 + g, -0.5 + g, indexing="ij")
+    r, z = R.ravel(), Z.ravel()
+    rng = np.random.default_rng(3)
+    S = rng.standard_normal((1, 4, r.size)) + 1j * rng.standard_normal((1, 4, r.size))
+    _check(r, z, r, z, S, 8, 4)
+
+
+@gpu
+def test_near_axis():
+    need_gpu()
+    r, z, S = inputs.paper_unit(800, 6, seed=8)
+    r = r.copy()
+    r[:10] = 1e-6 * (1 + np.arange(10))
+    _check(r, z, r, z, S, 10, 4, tol=1e-11)
+
+
+@gpu
+def test_auto_depth_rule():
+    """depth 0: the smallest d >= 2 with at most max_leaf points of each set
+    per leaf."""
+    need_gpu()
+    axf = _axf()
+    rs, zs, rf, zf, _ = inputs.annulus(3000, 2000, 2, seed=5)
+    for max_leaf in (16, 64, 300):
+        plan = axf.Plan(rs, zs, rf, zf, 2, 4, depth=0, max_leaf=max_leaf)
+        d = plan.info()["depth"]
+        rlo, zlo, L, invL = O.square_info(rs, zs, rf, zf)
+
+        def worst(level):
+            m = 0
+            for (a, b) in ((rs, zs), (rf, zf)):
+                ir, iz = O.box_indices(a, b, rlo, zlo, invL, level)
+                m = max(m, np.bincount(ir * (1 << level) + iz).max())
+            return m
+
+        assert worst(d) <= max_leaf or d == 11
+        if d > 2:
+            assert worst(d - 1) > max_leaf
+        plan.close()

@@ -73,3 +73,33 @@ def test_paper_setup_mode0():
     assert e12[0, 0] < 3e-8, e12
     assert e16[0, 0] < 1e-9, e16
     assert e16[0, 1] < e12[0, 1] / 10
+
+
+def test_fmm_gradient_converges_to_direct_gradient():
+    """d/dr and d/dz of the local expansion plus the near-field derivative
+    formulas of App. A approach the exact field gradient as M grows."""
+    r, z, S = inputs.ring_box(500, 4, nrhs=1, seed=12)
+    rf, zf = r[:120] + 7e-4, z[:120].copy()
+    gr, gz = O.direct_grad(r, z, rf, zf, S)
+    errs = []
+    for M in (6, 10, 14):
+        _, dr, dz = O.fmm_grad(r, z, rf, zf, S, M, 3)
+        e = max(np.abs(dr - gr).max() / np.abs(gr).max(), np.abs(dz - gz).max() / np.abs(gz).max())
+        errs.append(e)
+    assert errs[2] < 1e-6 and errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10, errs
+
+
+def test_fmm_transpose_on_shared_tree():
+    """With sources and field points on one tree, the FMM with roles swapped is
+    the exact transpose of the FMM (G is real and symmetric under
+    (r, r1, x) -> (r1, r, -x), and the near/far split is symmetric)."""
+    r, z, S = inputs.ring_box(600, 3, nrhs=2, seed=13)
+    rf = np.linspace(0.52, 1.48, 300)
+    zf = np.sin(np.linspace(0, 9, 300)) * 0.45
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal((2, 3, 300)) + 1j * rng.standard_normal((2, 3, 300))
+    phi = O.fmm(r, z, rf, zf, S, 7, 4)
+    gS = O.fmm(rf, zf, r, z, g, 7, 4)
+    lhs = np.real(np.vdot(g, phi))
+    rhs = np.real(np.vdot(gS, S))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
