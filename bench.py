@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 64 lanes x 2 (FMA)
-HEADLINE_ORDER = 22              # smallest M with max-over-modes error <= 1e-10 here
+HEADLINE_ORDER = 24              # smallest M with max-over-modes error <= 1e-10 here (M = 22: 1.6e-10)
 CONFIG_ORDER = 12
 
 
@@ -51,7 +51,44 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 200k-ring adjoint measurement")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(torch, mib):
+    """A plain copy kernel of known size, for scaling the HBM byte counters."""
+    n = mib * (1 << 20) // 8
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+
+
+def read_traffic(kernel_file):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "leaf_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2301_01179_amd", "csrc", kernel_file)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def autotune_depth(torch, axf, coords, S, nmodes, order, candidates):
@@ -106,6 +143,78 @@ def measure(torch, axf, coords, S, nmodes, order, depth, steps, warmup):
     return plan, phi, t_step, t_eval, timing
 
 
+def _median_time(torch, fn, reps):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def measure_adjoint(torch, axf, inputs, dev):
+    """Adjoint workload: 200,000 rings (sources = field points, ring-box
+    geometry), modes 0..16, M = 12; loss sum |phi - phi_target|^2.  Times the
+    forward evaluation and the adjoint (strength and coordinate gradients)."""
+    n, nm, M = 200_000, 17, 12
+    r, z, S = inputs.ring_box(n, nm, 1, seed=5)
+    _, _, St = inputs.ring_box(n, nm, 1, seed=6)
+    rt, zt = torch.from_numpy(r).to(dev), torch.from_numpy(z).to(dev)
+    S, St = torch.from_numpy(S).to(dev), torch.from_numpy(St).to(dev)
+    plan = axf.Plan(rt, zt, rt, zt, nm, M, depth=0, max_leaf=32)
+    phi_t = plan.evaluate(St)
+    state = {}
+
+    def fwd():
+        state["phi"] = plan.evaluate(S)
+
+    def adj():
+        g = 2 * (state["phi"] - phi_t)
+        state["grads"] = plan.adjoint(g, S)
+
+    fwd(); adj()
+    t_f = _median_time(torch, fwd, 5)
+    t_a = _median_time(torch, adj, 5)
+    units = float(n) * n * nm
+    out = {"workload": f"{n} rings = field points, ring box [0.5,1.5]x[-0.5,0.5], modes 0..{nm - 1}, M = {M}",
+           "depth": plan.info()["depth"], "ms_forward": t_f * 1e3, "ms_adjoint": t_a * 1e3,
+           "adjoint_value": units / t_a, "unit": "modal ring-pair interactions/s"}
+    plan.close()
+    return out
+
+
+def measure_batch(torch, axf, inputs, dev):
+    """Batched workload: 64 problems, sizes log-uniform in 1e3..2e5 rings of
+    the ring-box geometry (sources = field points), 1..8 right-hand sides,
+    modes 0..16, M = 12, depths from the autotuner.  Times the captured graph
+    replay against per-problem plain launches."""
+    nm, M = 17, 12
+    sizes, nrhs = inputs.batched_sizes(64, 1e3, 2e5, seed=4)
+    probs = []
+    units = 0.0
+    for i, (n, q) in enumerate(zip(sizes, nrhs)):
+        r, z, S = inputs.ring_box(int(n), nm, nrhs=int(q), seed=1000 + i)
+        probs.append((r, z, r, z, S))
+        units += float(n) * n * nm * q
+    t0 = time.perf_counter()
+    b = axf.Batch(probs, nm, M)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    b.launch()
+    b.launch_plain()
+    t_graph = _median_time(torch, b.launch, 7)
+    t_plain = _median_time(torch, b.launch_plain, 7)
+    out = {"workload": "64 problems, 1e3..2e5 rings log-uniform, nrhs 1..8, modes 0..16, M = 12",
+           "total_rings": int(sizes.sum()), "ms_graph": t_graph * 1e3, "ms_plain": t_plain * 1e3,
+           "graph_value": units / t_graph, "plain_value": units / t_plain,
+           "unit": "modal ring-pair interactions/s", "s_create": t_create,
+           "depths": b.depths()}
+    b.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +222,10 @@ def main():
               "design is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
 
     from paper_2301_01179_amd import axf, inputs
 
@@ -180,9 +293,10 @@ def main():
     dom = max(phases, key=lambda p: timing[p][0])
     ms_dom, launches = timing[dom]
     achieved = flops[dom] / (ms_dom / 1e3 / args.steps) / 1e12 if ms_dom > 0 else 0.0
+    traffic = read_traffic("axf_fmm.hip") if dom == "leaf" else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
-                "traffic": None, "kernel": dom,
+                "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(ms_dom / max(launches, 1), 4),
                 "launches_per_step": launches // max(args.steps, 1)}
 
@@ -198,6 +312,9 @@ def main():
                      "eval_only_value": units / te2, "ms_per_step": ts2 * 1e3,
                      "max_rel_err": float(e2), "fmm_vs_direct_speedup": t_direct / ts2}
         p2.close()
+
+    adjoint = None if args.no_adjoint else measure_adjoint(torch, axf, inputs, dev)
+    batch = None if args.no_batch else measure_batch(torch, axf, inputs, dev)
 
     line = {
         "metric": "modal ring-pair interactions/s at <=1e-10 rel err; FMM vs direct speedup",
@@ -226,6 +343,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "config_order_result": secondary,
+        "adjoint_result": adjoint,
+        "batch_result": batch,
     }
     if eps_oracle is not None:
         line["gpu_direct_vs_oracle"] = direct_parity

@@ -15,18 +15,23 @@ namespace axf {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
-// Coefficients of the downward recursion written for G:
-//   G^(n-1) = A[n] chi G^(n) - B[n] G^(n+1),  A[n] = 4n/(2n-1),  B[n] = (2n+1)/(2n-1).
+// Downward recursion of the modal Green's function,
+//   G^(n-1) = A_n chi G^(n) - B_n G^(n+1),  A_n = 4n/(2n-1),  B_n = (2n+1)/(2n-1),
+// in rescaled variables G^(n) = w_n z_n with w_(n-1) = B_n w_(n+1), which
+// turns every step into one multiply and one fma:
+//   z_(n-1) = alpha_n chi z_n - z_(n+1),  alpha_n = A_n rho_n,  rho_n = w_n / w_(n-1).
+// rho is anchored at the top (rho = 1 at kMillerMax + 1) and built downward
+// by rho_n = 1 / (B_n rho_(n+1)); each entry is consistent with its
+// neighbour to one rounding, which is all the rescaling needs.
 constexpr int kMillerMax = 1400;
 struct DownCoef {
-    double a[kMillerMax + 2];
-    double b[kMillerMax + 2];
-    constexpr DownCoef() : a(), b()
+    double alpha[kMillerMax + 2];
+    double rho[kMillerMax + 2];
+    constexpr DownCoef() : alpha(), rho()
     {
-        for (int n = 1; n < kMillerMax + 2; ++n) {
-            a[n] = 4.0 * n / (2.0 * n - 1.0);
-            b[n] = (2.0 * n + 1.0) / (2.0 * n - 1.0);
-        }
+        rho[kMillerMax + 1] = 1.0;
+        for (int n = kMillerMax; n >= 1; --n) rho[n] = (2.0 * n - 1.0) / ((2.0 * n + 1.0) * rho[n + 1]);
+        for (int n = 1; n < kMillerMax + 2; ++n) alpha[n] = 4.0 * n / (2.0 * n - 1.0) * rho[n];
     }
 };
 static __constant__ DownCoef c_down = DownCoef();
@@ -46,89 +51,6 @@ inline double forward_chi_limit(int nmodes)
     if (N < 2) return 1e300;
     double eta = 4.605170185988091 / (2.0 * N);   // ln(100) / (2N)
     return 0.5 * (__builtin_exp(eta) + __builtin_exp(-eta));
-}
-
-// Modal Green's functions of one pair per lane, G[n] for n < NMB (entries at
-// n >= nmodes are finite but unused).  Must be called by every lane of the
-// wave in uniform control flow (the backward branch uses a wave-wide step
-// count).  Inputs:
-//   rm2 = (r - r1)^2 + x^2 > 0,  rp2 = (r + r1)^2 + x^2,  rr = r r1,
-//   inv_rr = 1 / (r r1).
-template <int NMB>
-__device__ __forceinline__ void green_modes(double rm2, double rp2, double rr, double inv_rr,
-                                            double chistar, int nmodes, double (&G)[NMB])
-{
-    // AGM(rho+, rho-): G^(0) = 1 / (2 AGM), and with c_n the AGM half-differences
-    // G^(1) / G^(0) = (1 / (2 r r1)) sum_{n >= 1} 2^(n-1) c_n^2   (from E/K).
-    double rp = sqrt(rp2), rm = sqrt(rm2);
-    double a = rp, b = rm;
-    double c = 2.0 * rr / (rp + rm);          // c_1 = (rho+ - rho-) / 2, no cancellation
-    double csum = c * c, w = 1.0;
-    for (int it = 0; it < 48; ++it) {
-        double an = 0.5 * (a + b);
-        b = sqrt(a * b);
-        a = an;
-        if (c <= 0x1p-30 * a) break;
-        c = 0.5 * (a - b);
-        w *= 2.0;
-        csum = fma(w * c, c, csum);
-    }
-    double g0 = 0.5 / a;
-    double g1 = g0 * csum * 0.5 * inv_rr;
-    double chi = (rp2 + rm2) * 0.25 * inv_rr;
-
-    // forward recursion (all lanes; backward lanes overwrite below)
-    G[0] = g0;
-    if constexpr (NMB > 1) G[1] = g1;
-#pragma unroll
-    for (int n = 1; n + 1 < NMB; ++n) {
-        if (n + 1 < nmodes) {
-            const double fa = 4.0 * n / (2.0 * n + 1.0), fb = (2.0 * n - 1.0) / (2.0 * n + 1.0);
-            G[n + 1] = fa * chi * G[n] - fb * G[n - 1];
-        }
-    }
-    if constexpr (NMB > 2) {
-        bool back = chi >= chistar;
-        if (__ballot(back)) {
-            // chi - 1 without cancellation
-            double dchi = rm2 * 0.5 * inv_rr;
-            double dmin = wave_min(back ? dchi : 1e300);
-            // Miller start: error ~ lambda^(-2 (ntop - N)), acosh(1 + d) <= sqrt(2 d)
-            int extra = 10 + (int)ceil(20.0 / sqrt(2.0 * dmin));
-            int ntop = nmodes - 1 + extra;
-            if (ntop < NMB) ntop = NMB;
-            if (ntop > kMillerMax) ntop = kMillerMax;
-            ntop = __builtin_amdgcn_readfirstlane(ntop);
-            double yp = 0.0, y = 1.0;             // y_{ntop+1}, y_{ntop}
-            for (int n = ntop; n >= NMB; --n) {   // -> y_{NMB-1}
-                double ym = c_down.a[n] * chi * y - c_down.b[n] * yp;
-                yp = y;
-                y = ym;
-                if ((n & 7) == 0 && fabs(y) > 0x1p500) {
-                    y *= 0x1p-500;
-                    yp *= 0x1p-500;
-                }
-            }
-            // rescale so that the growth over the last NMB-1 steps stays in range
-            double lam = chi + sqrt(dchi * (chi + 1.0));
-            int e = ilogb(y) + (int)ceil((NMB - 1) * log2(lam)) - 16;
-            int emax = ilogb(y) + 1000;
-            if (e > emax) e = emax;
-            y = ldexp(y, -e);
-            yp = ldexp(yp, -e);
-            double Gb[NMB];
-            Gb[NMB - 1] = y;
-#pragma unroll
-            for (int n = NMB - 1; n >= 1; --n) {
-                const double fa = 4.0 * n / (2.0 * n - 1.0), fb = (2.0 * n + 1.0) / (2.0 * n - 1.0);
-                double up = (n == NMB - 1) ? yp : Gb[n + 1];
-                Gb[n - 1] = fa * chi * Gb[n] - fb * up;
-            }
-            double s = g0 / Gb[0];
-#pragma unroll
-            for (int n = 1; n < NMB; ++n) G[n] = back ? Gb[n] * s : G[n];
-        }
-    }
 }
 
 // sqrt and reciprocal for positive normal arguments: hardware estimate

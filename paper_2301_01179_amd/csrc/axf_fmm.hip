@@ -456,31 +456,46 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
     double scale = 0.0;
     if constexpr (NMB > 2) {
         if (anyback) {
-            double dmin = wave_min(back ? ps.dchi : 1e300);
-            int extra = 10 + (int)ceil(20.0 * __builtin_amdgcn_rsq(2.0 * dmin));
-            // steps above the stored modes, a multiple of 8 (more steps only
-            // add accuracy); coefficients of 8 steps are fetched together
+            // Miller's backward recursion, started from the large-n limit of
+            // the ratio G^(n+1)/G^(n) (from the hypergeometric form
+            // Q_(n-1/2)(cosh eta) ~ e^(-(n+1/2) eta) 2F1(1/2, n+1/2; n+1; e^(-2 eta))):
+            //   t_n ~ (n+1/2)/(n+1) e^(-eta) (1 + q / (4 (1-q) n (n+1))),  q = e^(-2 eta).
+            // Its error decays like e^(-2 eta) per step; 3 + 12/sqrt(2 (chi-1))
+            // steps above the top mode reach the rounding level (the bound
+            // acosh(1 + d) <= sqrt(2 d) makes the count conservative).
+            const double dmin = wave_min(back ? ps.dchi : 1e300);
+            int extra = 3 + (int)ceil(12.0 * __builtin_amdgcn_rsq(2.0 * dmin));
+            // steps above the stored modes, a multiple of 8
             int nsteps = nmodes - 1 + extra - (NMB - 1);
             nsteps = (nsteps + 7) & ~7;
             if (nsteps < 8) nsteps = 8;
             if (NMB - 1 + nsteps > kMillerMax) nsteps = (kMillerMax - NMB + 1) & ~7;
             const int ntop = __builtin_amdgcn_readfirstlane(NMB - 1 + nsteps);
-            const double chi = ps.chi;
-            double yp = 0.0, y = 1.0;
+            // lanes on the forward branch run the same steps on a harmless chi
+            const double dch = back ? ps.dchi : dmin;
+            const double chi = back ? ps.chi : 1.0 + dmin;
+            const double lam = chi + fast_sqrt(dch * (chi + 1.0));      // e^eta
+            const double il = fast_rcp(lam), q = il * il;
+            const double nt = (double)ntop;
+            const double t = (nt + 0.5) * fast_rcp(nt + 1.0) * il *
+                             fma(q, fast_rcp(4.0 * (1.0 - q) * nt * (nt + 1.0)), 1.0);
+            double zc = 1.0;                                  // z_ntop
+            double zp = t * fast_rcp(c_down.rho[ntop + 1]);   // z_(ntop+1)
             for (int n = ntop; n >= NMB; n -= 8) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const double ym = fma(c_down.a[n - u] * chi, y, -c_down.b[n - u] * yp);
-                    yp = y;
-                    y = ym;
+                    const double zm = fma(c_down.alpha[n - u] * chi, zc, -zp);
+                    zp = zc;
+                    zc = zm;
                 }
-                if (fabs(y) > 0x1p500) {
-                    y *= 0x1p-500;
-                    yp *= 0x1p-500;
+                if (fabs(zc) > 0x1p500) {
+                    zc *= 0x1p-500;
+                    zp *= 0x1p-500;
                 }
             }
+            // back to G-scaled values with w_(NMB-1) = 1: y_(NMB-1), y_NMB
+            double y = zc, yp = c_down.rho[NMB] * zp;
             // keep the growth of the last NMB-1 steps in range
-            double lam = chi + fast_sqrt(ps.dchi * (chi + 1.0));
             int e = ilogb(y) + (int)ceil((NMB - 1) * log2(lam)) - 16;
             int emax = ilogb(y) + 1000;
             if (e > emax) e = emax;
@@ -561,43 +576,50 @@ struct PairShape {
     static constexpr int RC = 16;       // modes per reduction round
 };
 
-// Deterministic sum of the block's waves' accumulators through LDS (in
-// rounds of RC modes); wave 0 ends with the totals.
-template <int NMB, int MODE, int WPB>
-__device__ __forceinline__ void reduce_waves(Acc<NMB, MODE> &A, double *__restrict__ buf)
+// Deterministic sum of the block's waves' accumulators through LDS, in
+// rounds of RC modes [N0, N1); wave 0 ends with the totals.  The rounds are
+// unrolled at compile time so that every accumulator index is a constant
+// (a runtime mode index would move the accumulators to scratch memory).
+template <int NMB, int MODE, int WPB, int N0>
+__device__ __forceinline__ void reduce_round(Acc<NMB, MODE> &A, double *__restrict__ buf, int w, int lane)
 {
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     constexpr int K = MODE ? 6 : 2;
     constexpr int RC = PairShape<NMB>::RC;
+    constexpr int N1 = N0 + RC < NMB ? N0 + RC : NMB;
+    for (int src = WPB - 1; src >= 0; --src) {
+        __syncthreads();
+        if (w == src) {
 #pragma unroll
-    for (int n0 = 0; n0 < NMB; n0 += RC) {
-        for (int src = WPB - 1; src >= 0; --src) {
-            __syncthreads();
-            if (w == src) {
+            for (int n = N0; n < N1; ++n) {
+                double *bp = buf + ((size_t)(n - N0) * 64 + lane) * K;
+                double v[6] = {A.ar[n], A.ai[n], 0, 0, 0, 0};
+                if constexpr (MODE != 0) {
+                    v[2] = A.rr_[n]; v[3] = A.ri_[n]; v[4] = A.zr_[n]; v[5] = A.zi_[n];
+                }
+                if (src == WPB - 1) {
 #pragma unroll
-                for (int n = n0; n < n0 + RC && n < NMB; ++n) {
-                    double *bp = buf + ((size_t)(n - n0) * 64 + lane) * K;
-                    double v[6] = {A.ar[n], A.ai[n], 0, 0, 0, 0};
+                    for (int k = 0; k < K; ++k) bp[k] = v[k];
+                } else if (src > 0) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) bp[k] += v[k];
+                } else {
+                    A.ar[n] += bp[0];
+                    A.ai[n] += bp[1];
                     if constexpr (MODE != 0) {
-                        v[2] = A.rr_[n]; v[3] = A.ri_[n]; v[4] = A.zr_[n]; v[5] = A.zi_[n];
-                    }
-                    if (src == WPB - 1) {
-#pragma unroll
-                        for (int k = 0; k < K; ++k) bp[k] = v[k];
-                    } else if (src > 0) {
-#pragma unroll
-                        for (int k = 0; k < K; ++k) bp[k] += v[k];
-                    } else {
-                        A.ar[n] += bp[0];
-                        A.ai[n] += bp[1];
-                        if constexpr (MODE != 0) {
-                            A.rr_[n] += bp[2]; A.ri_[n] += bp[3]; A.zr_[n] += bp[4]; A.zi_[n] += bp[5];
-                        }
+                        A.rr_[n] += bp[2]; A.ri_[n] += bp[3]; A.zr_[n] += bp[4]; A.zi_[n] += bp[5];
                     }
                 }
             }
         }
     }
+    if constexpr (N1 < NMB) reduce_round<NMB, MODE, WPB, N1>(A, buf, w, lane);
+}
+
+template <int NMB, int MODE, int WPB>
+__device__ __forceinline__ void reduce_waves(Acc<NMB, MODE> &A, double *__restrict__ buf)
+{
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    reduce_round<NMB, MODE, WPB, 0>(A, buf, w, lane);
     __syncthreads();
 }
 

@@ -102,3 +102,45 @@ def test_table_scaling():
     f = s ** (1 + a + b + c)
     scale = np.abs(T).max()
     np.testing.assert_allclose(Ts * f, T, rtol=1e-12, atol=1e-14 * scale)
+
+
+def _x_series_equal_radii(n, r, x0, K):
+    """Taylor coefficients in t of G^(n)(r, r, x0 + t), k = 0..K, by a route
+    that shares nothing with the table recursion: with r = r1,
+    G = Q_{n-1/2}(chi) / (2 pi r) and chi = 1 + x^2 / (2 r^2).  The Taylor
+    series of Q_nu about chi0 follows from Legendre's equation
+    (1 - chi^2) Q'' - 2 chi Q' + nu (nu + 1) Q = 0, started from Q_nu(chi0)
+    and Q_nu'(chi0) = nu (chi0 Q_nu - Q_{nu-1}) / (chi0^2 - 1) (hypergeometric
+    values), then composed with chi(x0 + t) = chi0 + (x0 t + t^2 / 2) / r^2."""
+    r, x0 = mp.mpf(r), mp.mpf(x0)
+    chi0 = 1 + x0 * x0 / (2 * r * r)
+    nu = n - mp.mpf(1) / 2
+    q = lambda m: g_mp(abs(m), r, r, x0) * 2 * mp.pi * r      # Q_{-m-1/2} = Q_{m-1/2}
+    a = [q(n), nu * (chi0 * q(n) - q(n - 1)) / (chi0 ** 2 - 1)]
+    for j in range(K - 1):
+        a.append((2 * chi0 * (j + 1) ** 2 * a[j + 1] + (j * (j + 1) - nu * (nu + 1)) * a[j])
+                 / ((1 - chi0 ** 2) * (j + 2) * (j + 1)))
+    c1, c2 = x0 / (r * r), 1 / (2 * r * r)
+    out = [mp.mpf(0)] * (K + 1)
+    p = [mp.mpf(1)] + [mp.mpf(0)] * K          # (c1 t + c2 t^2)^j, truncated at t^K
+    for j in range(K + 1):
+        for k in range(K + 1):
+            out[k] += a[j] * p[k]
+        p = [(c1 * p[k - 1] if k >= 1 else 0) + (c2 * p[k - 2] if k >= 2 else 0) for k in range(K + 1)]
+    return [v / (2 * mp.pi * r) for v in out]
+
+
+@pytest.mark.parametrize("r,x0", [(60.0, 2.0), (430.0, 3.0)])
+def test_table_far_from_axis_high_order(r, x0):
+    """Far from the axis relative to the separation, neighbouring modes agree
+    to many digits and the starting formulas amplify FP64 rounding by up to
+    ~1e14 (errors of 1e-2 at order 22 for r = 60, x = 2, n = 32).  The
+    table's x column must still match an independent 80-digit series."""
+    N, M = 32, 16
+    T = O.gtable(N, M, r, r, x0)
+    with mp.workdps(80):
+        for n in (0, 1, 16, 31, 32):
+            ref = _x_series_equal_radii(n, r, x0, 2 * M)
+            for k in range(2 * M + 1):
+                rv = float(ref[k])
+                assert abs(T[n, 0, 0, k] - rv) <= 1e-14 * abs(rv), (n, k, T[n, 0, 0, k], rv)
