@@ -230,17 +230,19 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
         // descriptors and merged queues
         std::vector<ProbDev> pd(nprob);
         std::vector<int2> qg, qp, ql;
-        std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qs(AXF_MAX_DEPTH + 1);
+        std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qs(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1);
         for (int i = 0; i < nprob; ++i) {
             const Plan &pl = *b->plans[i];
             fill_probdev(pl, problems[i].S, problems[i].phi, pd[i]);
             int64_t ge = pl.src.n * pl.Cs;
             for (int64_t k = 0; k * 256 < ge; ++k) qg.push_back(make_int2(i, (int)k));
-            for (int k = 0; k < pl.src.nocc[pl.d]; ++k) qp.push_back(make_int2(i, k));
+            for (int k = 0; k < pl.src.nocc[pl.d] * pl.C; ++k) qp.push_back(make_int2(i, k));
             for (int t = 1; pl.d - t >= 2; ++t)
-                for (int k = 0; k < pl.src.nocc[pl.d - t]; ++k) qm[t].push_back(make_int2(i, k));
-            for (int l = 2; l <= pl.d; ++l)
+                for (int k = 0; k < pl.src.nocc[pl.d - t] * pl.C; ++k) qm[t].push_back(make_int2(i, k));
+            for (int l = 2; l <= pl.d; ++l) {
+                for (int k = 0; k < pl.fld.nocc[l] * pl.C; ++k) qlt[l].push_back(make_int2(i, k));
                 for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k) qs[l].push_back(make_int2(i, k));
+            }
             for (int k = 0; k < pl.fld.nchunks; ++k) ql.push_back(make_int2(i, k));
         }
         Sizer sz;
@@ -251,6 +253,7 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
         for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
             sz.add<int2>(qm[l].size() + 1);
             sz.add<int2>(qs[l].size() + 1);
+            sz.add<int2>(qlt[l].size() + 1);
         }
         b->qmem = arena_acquire(sz.bytes + 4096);
         BatchQueues &q = b->q;
@@ -267,6 +270,7 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
         for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
             up(qm[l], q.m2m[l], q.nm2m[l]);
             up(qs[l], q.s2l[l], q.ns2l[l]);
+            up(qlt[l], q.l2l[l], q.nl2l[l]);
         }
         AXF_HIP(hipStreamSynchronize(st));
         q.probs = dp;

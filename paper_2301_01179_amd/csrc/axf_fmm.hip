@@ -36,87 +36,72 @@ __global__ void k_gather(const double2 *__restrict__ S, const int32_t *__restric
 }
 
 // ------------------------------------------------------------------- P2M
-constexpr int kP2MChunk = 32;
+// Leaf moments (eq. analysis:moments in box units): one block per (leaf,
+// channel), s_ij = sum_s S_s (dr_s)^i (dz_s)^j / j!, offsets in leaf units.
+constexpr int kP2MChunk = 64;
 __device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double rlo, double zlo, double invh,
                                          SideView sv, const int32_t *__restrict__ boxes,
                                          const double2 *__restrict__ Sg, double2 *__restrict__ mom, int item)
 {
     __shared__ double pr[kP2MChunk][AXF_MAX_ORDER + 1];
     __shared__ double pz[kP2MChunk][AXF_MAX_ORDER + 1];
+    __shared__ double2 ss[kP2MChunk];
     const int P = (M + 1) * (M + 2) / 2;
-    const int k = item;
+    const int k = item / C, c = item - (item / C) * C;
     const int b = boxes[k];
     const int nb = 1 << depth;
     const int ir = b / nb, iz = b - ir * nb;
     const uint32_t m = morton((uint32_t)ir, (uint32_t)iz);
     const int first = sv.off[m], last = sv.off[m + 1];
     const double cr = ir + 0.5, cz = iz + 0.5;
-    const int nout = C * P;
-    constexpr int kOut = 8;
-    double2 acc[kOut];
-    int oc[kOut], oi[kOut], oj[kOut];
+    // this thread's outputs: p = tid and tid + 256
+    int oi[2], oj[2];
 #pragma unroll
-    for (int u = 0; u < kOut; ++u) {
-        acc[u] = make_double2(0.0, 0.0);
-        int e = threadIdx.x + u * 256;
-        int c = e / P, p = e - c * P;
-        int i = 0;
-        while (p >= M + 1 - i) {
-            p -= M + 1 - i;
-            ++i;
-        }
-        oc[u] = c;
+    for (int u = 0; u < 2; ++u) {
+        int p = threadIdx.x + u * 256, i = 0;
+        if (p < P)
+            while (p >= M + 1 - i) {
+                p -= M + 1 - i;
+                ++i;
+            }
         oi[u] = i;
         oj[u] = p;
     }
-    for (int base = 0; base < nout; base += kOut * 256) {
-        for (int s0 = first; s0 < last; s0 += kP2MChunk) {
-            int ns = min(kP2MChunk, last - s0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < ns; e += blockDim.x) {
-                double dr = (sv.r[s0 + e] - rlo) * invh - cr;
-                double dz = (sv.z[s0 + e] - zlo) * invh - cz;
-                double a = 1.0, c = 1.0;
-                for (int i = 0; i <= M; ++i) {
-                    pr[e][i] = a;
-                    pz[e][i] = c;
-                    a *= dr;
-                    c *= dz / (i + 1.0);
-                }
+    double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    for (int s0 = first; s0 < last; s0 += kP2MChunk) {
+        const int ns = min(kP2MChunk, last - s0);
+        __syncthreads();
+        if (threadIdx.x < ns) {
+            const int e = threadIdx.x;
+            const double dr = (sv.r[s0 + e] - rlo) * invh - cr;
+            const double dz = (sv.z[s0 + e] - zlo) * invh - cz;
+            double a = 1.0, q = 1.0;
+            for (int i = 0; i <= M; ++i) {
+                pr[e][i] = a;
+                pz[e][i] = q;
+                a *= dr;
+                q *= dz / (i + 1.0);
             }
-            __syncthreads();
+            ss[e] = Sg[(int64_t)(s0 + e) * Cs + c];
+        }
+        __syncthreads();
 #pragma unroll
-            for (int u = 0; u < kOut; ++u) {
-                int e = base + threadIdx.x + u * 256;
-                if (e < nout) {
-                    int c = (base == 0) ? oc[u] : e / P;
-                    int i = oi[u], j = oj[u];
-                    if (base != 0) {
-                        int p = e - c * P;
-                        i = 0;
-                        while (p >= M + 1 - i) {
-                            p -= M + 1 - i;
-                            ++i;
-                        }
-                        j = p;
-                    }
-                    double2 a = acc[u];
-                    for (int s = 0; s < ns; ++s) {
-                        double w = pr[s][i] * pz[s][j];
-                        double2 sv2 = Sg[(int64_t)(s0 + s) * Cs + c];
-                        a.x += w * sv2.x;
-                        a.y += w * sv2.y;
-                    }
-                    acc[u] = a;
-                }
+        for (int u = 0; u < 2; ++u) {
+            if (threadIdx.x + u * 256 >= P) continue;
+            const int i = oi[u], j = oj[u];
+            double2 a = acc[u];
+            for (int s = 0; s < ns; ++s) {
+                const double w = pr[s][i] * pz[s][j];
+                a.x = fma(w, ss[s].x, a.x);
+                a.y = fma(w, ss[s].y, a.y);
             }
+            acc[u] = a;
         }
+    }
 #pragma unroll
-        for (int u = 0; u < kOut; ++u) {
-            int e = base + threadIdx.x + u * 256;
-            if (e < nout) mom[(int64_t)k * nout + e] = acc[u];
-            acc[u] = make_double2(0.0, 0.0);
-        }
+    for (int u = 0; u < 2; ++u) {
+        const int p = threadIdx.x + u * 256;
+        if (p < P) mom[((int64_t)k * C + c) * P + p] = acc[u];
     }
 }
 
@@ -127,17 +112,37 @@ __global__ __launch_bounds__(256) void k_p2m(int M, int C, int Cs, int depth, do
     p2m_body(M, C, Cs, depth, rlo, zlo, invh, sv, boxes, Sg, mom, blockIdx.x);
 }
 
+// Decode a packed-triangle index p into (i, j), i + j <= M, i-major.
+__device__ __forceinline__ void tri_decode(int M, int p, int &i, int &j)
+{
+    int r = 0;
+    while (p >= M + 1 - r) {
+        p -= M + 1 - r;
+        ++r;
+    }
+    i = r;
+    j = p;
+}
+
 // ------------------------------------------------------------------- M2M
-// parent s_ij = sum_children sum_a C(i,a) dr^(i-a) 2^-a sum_b dz^(j-b)/(j-b)! 2^-b s'_ab
-// with dr, dz = +-1/4 (child centre - parent centre in parent units).
+// Upward shift (eq. analysis:shift) of the four children into the parent,
+// in parent units with child offsets dr, dz = +-1/4:
+//   s_ij = sum_children sum_a R[i][a] sum_b Z[j][b] s'_ab,
+//   R[i][a] = C(i,a) dr^(i-a) 2^-a,  Z[j][b] = dz^(j-b) / (j-b)! 2^-b.
+// The double sum is applied separably: first over b for each child, summed
+// over the two children of each r offset, then over a.  One block per
+// (parent box, channel); the children's moments are staged in LDS.
 __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t *__restrict__ pboxes,
                                          const int32_t *__restrict__ cslot, const double2 *__restrict__ cmom,
                                          double2 *__restrict__ pmom, int item)
 {
+    constexpr int PM = (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 2) / 2;
     __shared__ double cfr[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
     __shared__ double cfz[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
+    __shared__ double2 sm[4][PM];
+    __shared__ double2 t[2][PM];
     const int P = (M + 1) * (M + 2) / 2;
-    const int k = item;
+    const int k = item / C, c = item - (item / C) * C;
     const int b = pboxes[k];
     const int nb = 1 << level;
     const int ir = b / nb, iz = b - ir * nb;
@@ -148,10 +153,10 @@ __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t 
         double vr = 0.0, vz = 0.0;
         if (a <= i) {
             double bin = 1.0, pw = 1.0, fct = 1.0;
-            for (int t = 0; t < a; ++t) bin = bin * (i - t) / (t + 1.0);
-            for (int t = 0; t < i - a; ++t) {
+            for (int q = 0; q < a; ++q) bin = bin * (i - q) / (q + 1.0);
+            for (int q = 0; q < i - a; ++q) {
                 pw *= d;
-                fct *= (t + 1.0);
+                fct *= (q + 1.0);
             }
             double two = ldexp(1.0, -a);
             vr = bin * pw * two;
@@ -160,39 +165,49 @@ __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t 
         cfr[sg][i][a] = vr;
         cfz[sg][i][a] = vz;
     }
-    __syncthreads();
     const int cnb = nb * 2;
-    int cs[4];
-    for (int ch = 0; ch < 4; ++ch) {
-        int cr = ch >> 1, cz = ch & 1;
-        cs[ch] = cslot[(2 * ir + cr) * cnb + (2 * iz + cz)];
+    for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
+        const int ch = e / P, p = e - ch * P;
+        const int cs = cslot[(2 * ir + (ch >> 1)) * cnb + (2 * iz + (ch & 1))];
+        sm[ch][p] = cs >= 0 ? cmom[((int64_t)cs * C + c) * P + p] : make_double2(0.0, 0.0);
     }
-    const int nout = C * P;
-    for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-        int c = e / P, p = e - c * P;
-        int i = 0;
-        while (p >= M + 1 - i) {
-            p -= M + 1 - i;
-            ++i;
-        }
-        int j = p;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int ch = 0; ch < 4; ++ch) {
-            if (cs[ch] < 0) continue;
-            int sr = ch >> 1, sz = ch & 1;
-            const double2 *src = cmom + ((int64_t)cs[ch] * C + c) * P;
-            for (int a = 0; a <= i; ++a) {
-                double fr = cfr[sr][i][a];
-                int rowa = tri_index(M, a, 0);
-                for (int bb = 0; bb <= j; ++bb) {
-                    double w = fr * cfz[sz][j][bb];
-                    double2 v = src[rowa + bb];
-                    acc.x += w * v.x;
-                    acc.y += w * v.y;
-                }
+    __syncthreads();
+    // z pass: t[sr][a][j] = sum_sz sum_{b <= j} Z_sz[j][b] s'_(sr,sz)[a][b],  a + j <= M
+    for (int e = threadIdx.x; e < 2 * P; e += blockDim.x) {
+        const int sr = e / P, p = e - sr * P;
+        int a, j;
+        tri_decode(M, p, a, j);
+        const int row = p - j;          // tri_index(M, a, 0)
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int sz = 0; sz < 2; ++sz) {
+            const double2 *src = sm[sr * 2 + sz] + row;
+            for (int q = 0; q <= j; ++q) {
+                const double w = cfz[sz][j][q];
+                v.x = fma(w, src[q].x, v.x);
+                v.y = fma(w, src[q].y, v.y);
             }
         }
-        pmom[(int64_t)k * nout + e] = acc;
+        t[sr][p] = v;
+    }
+    __syncthreads();
+    // r pass: s[i][j] = sum_sr sum_{a <= i} R_sr[i][a] t[sr][a][j]
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        int i, j;
+        tri_decode(M, p, i, j);
+        double2 v = make_double2(0.0, 0.0);
+        int row = 0;                    // tri_index(M, a, 0)
+        for (int a = 0; a <= i; ++a) {
+#pragma unroll
+            for (int sr = 0; sr < 2; ++sr) {
+                const double w = cfr[sr][i][a];
+                const double2 x = t[sr][row + j];
+                v.x = fma(w, x.x, v.x);
+                v.y = fma(w, x.y, v.y);
+            }
+            row += M + 1 - a;
+        }
+        pmom[((int64_t)k * C + c) * P + p] = v;
     }
 }
 
@@ -203,31 +218,113 @@ __global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int3
     m2m_body(M, C, level, pboxes, cslot, cmom, pmom, blockIdx.x);
 }
 
+// ------------------------------------------------------------------- L2L
+// Local shift (eq. analysis:l2l) from the parent into each occupied target
+// box of a level, child offsets dr, dz = +-1/4 parent units, child units half
+// the parent's:  L'_kl = sum_a sum_q F_r[k][a] F_z[l][q] L_(k+a, l+q),
+// F[i][q] = C(i+q, q) d^q 2^-i.  Separable: over a, then over q.  Boxes
+// without a parent expansion (level 2) start from zero.  One block per
+// (target box, channel); the result initialises the box's locals, which the
+// S2L pass of the same level then accumulates into.
+__device__ __forceinline__ void l2l_body(int M, int C, int level, const int32_t *__restrict__ tbox,
+                                         const int32_t *__restrict__ tslot_parent, const double2 *__restrict__ ploc,
+                                         double2 *__restrict__ loc, int item)
+{
+    constexpr int PM = (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 2) / 2;
+    __shared__ double fc[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
+    __shared__ double2 pl[PM];
+    __shared__ double2 u[PM];
+    const int P = (M + 1) * (M + 2) / 2;
+    const int k = item / C, c = item - (item / C) * C;
+    double2 *out = loc + ((int64_t)k * C + c) * P;
+    const int nb = 1 << level;
+    const int bid = tbox[k];
+    const int ir = bid / nb, iz = bid - ir * nb;
+    const int pslot = level > 2 ? tslot_parent[(ir >> 1) * (nb >> 1) + (iz >> 1)] : -1;
+    if (pslot < 0) {                    // uniform over the block
+        for (int p = threadIdx.x; p < P; p += blockDim.x) out[p] = make_double2(0.0, 0.0);
+        return;
+    }
+    for (int e = threadIdx.x; e < 2 * (M + 1) * (M + 1); e += blockDim.x) {
+        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
+        int i = rem / (M + 1), q = rem - i * (M + 1);
+        double d = sg ? 0.25 : -0.25, v = 0.0;
+        if (i + q <= M) {
+            double bin = 1.0, pw = 1.0;
+            for (int s = 0; s < q; ++s) {
+                bin = bin * (i + q - s) / (s + 1.0);
+                pw *= d;
+            }
+            v = bin * pw * ldexp(1.0, -i);
+        }
+        fc[sg][i][q] = v;
+    }
+    const double2 *src = ploc + ((int64_t)pslot * C + c) * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) pl[p] = src[p];
+    __syncthreads();
+    const int sr = ir & 1, sz = iz & 1;
+    // r pass: u[kk][l] = sum_a F_r[kk][a] L[kk+a][l],  kk + a + l <= M
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        int kk, l;
+        tri_decode(M, p, kk, l);
+        double2 v = make_double2(0.0, 0.0);
+        int row = p - l;                // tri_index(M, kk, 0)
+        for (int a = 0; kk + a + l <= M; ++a) {
+            const double w = fc[sr][kk][a];
+            const double2 x = pl[row + l];
+            v.x = fma(w, x.x, v.x);
+            v.y = fma(w, x.y, v.y);
+            row += M + 1 - (kk + a);
+        }
+        u[p] = v;
+    }
+    __syncthreads();
+    // z pass: L'[kk][l] = sum_q F_z[l][q] u[kk][l+q]
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        int kk, l;
+        tri_decode(M, p, kk, l);
+        double2 v = make_double2(0.0, 0.0);
+        for (int q = 0; kk + l + q <= M; ++q) {
+            const double w = fc[sz][l][q];
+            const double2 x = u[p + q];
+            v.x = fma(w, x.x, v.x);
+            v.y = fma(w, x.y, v.y);
+        }
+        out[p] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int32_t *__restrict__ tbox,
+                                            const int32_t *__restrict__ tslot_parent,
+                                            const double2 *__restrict__ ploc, double2 *__restrict__ loc)
+{
+    l2l_body(M, C, level, tbox, tslot_parent, ploc, loc, blockIdx.x);
+}
+
 // ------------------------------------------------------- S2L, tiled form
-// One wave per (tile, channel).  A tile is up to TB occupied target boxes of
-// one radial station with the same z parity, so that every box of the tile
-// has the same interaction-list offsets (dr, dz) and therefore, for each
-// offset, the same operator: one table, one orientation.  Lane L owns the
-// outputs (k, l0 .. l0+LB-1) of all TB boxes; for each input moment (i, j)
-// the table values T[k][i][j+l] of the lane's outputs form a window that
-// slides by one entry per j (Hankel structure), so each step loads one table
-// value and does 2 LB TB FMAs on moments broadcast from LDS.  The forward
-// sign (-1)^(j+l) is split into (-1)^j on the staged moments and (-1)^l on
-// the accumulators.
+// One block of W waves per (tile, channel).  A tile is up to TB occupied
+// target boxes of one radial station with the same z parity, so that every
+// box of the tile has the same interaction-list offsets (dr, dz) and
+// therefore, for each offset, the same operator: one table, one
+// orientation.  Each lane owns the outputs (k, l0 .. l0+LB-1) of all TB
+// boxes (the W waves split the output rows between them, so the table is
+// not read twice); for each input moment (i, j) the table values T[k][i][j+l]
+// of the lane's outputs form a window that slides by one entry per j (Hankel
+// structure), so each step loads one table value and does 2 LB TB FMAs on
+// moments broadcast from LDS.  The forward sign (-1)^(j+l) is split into
+// (-1)^j on the staged moments and (-1)^l on the accumulators.  The result,
+// times (-1)^l / l!, is added to the locals that the L2L pass initialised.
 template <int LB, int TB>
 __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int level, int TS,
                                                  const int4 *__restrict__ tiles,      // station, parity, first, count
                                                  const int32_t *__restrict__ tslots,  // target slots of the tiles
                                                  const int32_t *__restrict__ tbox,    // slot -> box id (targets)
-                                                 const int32_t *__restrict__ tslot_parent,
-                                                 const double2 *__restrict__ ploc,
                                                  const int32_t *__restrict__ sslot,
                                                  const double2 *__restrict__ mom,
                                                  const double *__restrict__ tab,
                                                  double2 *__restrict__ loc, int item)
 {
     extern __shared__ double2 ms[];          // [TB][P] staged moments
-    __shared__ double lcoef[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
     __shared__ double invfact[AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
@@ -236,29 +333,15 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
     const int4 tl = tiles[ti];
     const int station = tl.x, nbx = tl.w;
     const int nb = 1 << level;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
 
-    if (lane <= M) {
+    if (tid <= M) {
         double f = 1.0;
-        for (int t = 2; t <= lane; ++t) f *= t;
-        invfact[lane] = 1.0 / f;
-    }
-    for (int e = lane; e < 2 * (M + 1) * (M + 1); e += 64) {
-        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
-        int i = rem / (M + 1), q = rem - i * (M + 1);
-        double d = sg ? 0.25 : -0.25, v = 0.0;
-        if (i + q <= M) {
-            double bin = 1.0, pw = 1.0;
-            for (int t = 0; t < q; ++t) {
-                bin = bin * (i + q - t) / (t + 1.0);
-                pw *= d;
-            }
-            v = bin * pw * ldexp(1.0, -i);
-        }
-        lcoef[sg][i][q] = v;
+        for (int t = 2; t <= tid; ++t) f *= t;
+        invfact[tid] = 1.0 / f;
     }
     // this lane's outputs: row k, columns l0 .. l0 + LB - 1
-    int k = 0, l0 = 0, acc_lane = lane;
+    int k = 0, l0 = 0, acc_lane = tid;
     bool live = false;
     for (int kk = 0; kk <= M; ++kk) {
         int nblk = (M + 1 - kk + LB - 1) / LB;
@@ -306,7 +389,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
             const int adr = outward ? -dr : dr, adz = dz < 0 ? -dz : dz;
             const double *T = tab_n + ((size_t)inner * 12 + geom_slot(adr, adz)) * nmodes * (size_t)TS;
             __syncthreads();
-            for (int e = lane; e < TB * P; e += 64) {
+            for (int e = tid; e < TB * P; e += nthr) {
                 int b = e / P, p = e - b * P;
                 double2 v = make_double2(0.0, 0.0);
                 if (ss[b] >= 0) v = mom[((int64_t)ss[b] * C + c) * P + p];
@@ -364,50 +447,33 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
             }
         }
     }
-    __syncthreads();
-    // write: (-1)^l / l! * acc + parent's local shifted (eq. analysis:l2l)
+    __syncthreads();                            // invfact is visible even when no offset ran
+    // add (-1)^l / l! * acc to the locals (each output has exactly one owner)
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
         if (!live || sl[b] < 0) continue;
-        const int bid = tbox[sl[b]];
-        const int ir = bid / nb, iz = bid - ir * nb;
-        int pslot = -1;
-        if (level > 2) pslot = tslot_parent[(ir >> 1) * (nb >> 1) + (iz >> 1)];
-        const int sr = ir & 1, sz = iz & 1;
-        const double2 *pl = pslot >= 0 ? ploc + ((int64_t)pslot * C + c) * P : nullptr;
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
             const int ll = l0 + u;
             if (ll > M - k) continue;
             const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
-            double2 v = make_double2(f * acc[u][b].x, f * acc[u][b].y);
-            if (pl) {
-                for (int a = 0; k + a <= M; ++a) {
-                    const double fa = lcoef[sr][k][a];
-                    for (int c2 = 0; k + a + ll + c2 <= M; ++c2) {
-                        const double wgt = fa * lcoef[sz][ll][c2];
-                        const double2 x = pl[tri_index(M, k + a, ll + c2)];
-                        v.x = fma(wgt, x.x, v.x);
-                        v.y = fma(wgt, x.y, v.y);
-                    }
-                }
-            }
-            loc[((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll)] = v;
+            double2 *o = loc + ((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll);
+            double2 v = *o;
+            v.x = fma(f, acc[u][b].x, v.x);
+            v.y = fma(f, acc[u][b].y, v.y);
+            *o = v;
         }
     }
 }
 
 template <int LB, int TB>
-__global__ __launch_bounds__(64) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
-                                                 const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
-                                                 const int32_t *__restrict__ tbox,
-                                                 const int32_t *__restrict__ tslot_parent,
-                                                 const double2 *__restrict__ ploc, const int32_t *__restrict__ sslot,
-                                                 const double2 *__restrict__ mom, const double *__restrict__ tab,
-                                                 double2 *__restrict__ loc)
+__global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
+                                                  const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
+                                                  const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
+                                                  const double2 *__restrict__ mom, const double *__restrict__ tab,
+                                                  double2 *__restrict__ loc)
 {
-    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, tslot_parent, ploc, sslot, mom, tab,
-                          loc, blockIdx.x);
+    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x);
 }
 
 // ------------------------------------------------------------ pair sums
@@ -858,23 +924,20 @@ template <int LB, int TB>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     size_t shm = sizeof(double2) * (size_t)TB * pl.P;
-    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C, 64, shm, st>>>(
-        pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l],
-        l > 2 ? tgt.slot[l - 1] : nullptr, l > 2 ? pl.lev[l - 1].loc : nullptr, src.slot[l], pl.lev[l].mom,
-        pl.lev[l].tab, pl.lev[l].loc);
+    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C, 64 * s2l_waves(pl.M), shm, st>>>(
+        pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],
+        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc);
 }
 
 void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
+    // locals of the level's target boxes: shifted parent expansion, or zero
+    k_l2l<<<tgt.nocc[l] * pl.C, 256, 0, st>>>(pl.M, pl.C, l, tgt.box[l], l > 2 ? tgt.slot[l - 1] : nullptr,
+                                               l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
     switch (s2l_lb(pl.M)) {
     case 1: launch_s2l_t<1, 8>(pl, src, tgt, l, st); break;
     case 2: launch_s2l_t<2, 8>(pl, src, tgt, l, st); break;
-    case 3: launch_s2l_t<3, 8>(pl, src, tgt, l, st); break;
-    case 4: launch_s2l_t<4, 4>(pl, src, tgt, l, st); break;
-    case 5: launch_s2l_t<5, 4>(pl, src, tgt, l, st); break;
-    case 6: launch_s2l_t<6, 4>(pl, src, tgt, l, st); break;
-    case 7: launch_s2l_t<7, 4>(pl, src, tgt, l, st); break;
-    default: launch_s2l_t<8, 4>(pl, src, tgt, l, st); break;
+    default: launch_s2l_t<3, 8>(pl, src, tgt, l, st); break;
     }
 }
 
@@ -967,16 +1030,27 @@ __global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, con
 }
 
 template <int LB, int TB>
-__global__ __launch_bounds__(64) void kb_s2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
-                                            int nmodes, int TS, int l)
+__global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
+                                             int nmodes, int TS, int l)
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
         const ProbDev &pd = P[it.x];
         __syncthreads();
-        s2l_tile_body<LB, TB>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l],
-                              l > 2 ? pd.tslot[l - 1] : nullptr, l > 2 ? pd.loc[l - 1] : nullptr, pd.sslot[l],
+        s2l_tile_body<LB, TB>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
                               pd.mom[l], pd.tab[l], pd.loc[l], it.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_l2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
+                                             int l)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        const ProbDev &pd = P[it.x];
+        __syncthreads();
+        l2l_body(M, pd.C, l, pd.tbox[l], l > 2 ? pd.tslot[l - 1] : nullptr, l > 2 ? pd.loc[l - 1] : nullptr,
+                 pd.loc[l], it.y);
     }
 }
 
@@ -1001,7 +1075,7 @@ void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
     const int P = (bq.M + 1) * (bq.M + 2) / 2;
     size_t shm = sizeof(double2) * (size_t)TB * P;
     int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
-    kb_s2l<LB, TB><<<g, 64, shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
+    kb_s2l<LB, TB><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }
 
 template <int NMB>
@@ -1036,14 +1110,14 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
     SideView sv = view_of(src);
     if (src.nocc[d] > 0) {
         PhaseTimer tm(pl, st, AXF_PHASE_P2M);
-        k_p2m<<<src.nocc[d], 256, 0, st>>>(M, C, pl.Cs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
+        k_p2m<<<src.nocc[d] * C, 256, 0, st>>>(M, C, pl.Cs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
                                            pl.Sg, pl.lev[d].mom);
     }
     {
         PhaseTimer tm(pl, st, AXF_PHASE_M2M);
         for (int l = d - 1; l >= 2; --l)
             if (src.nocc[l] > 0)
-                k_m2m<<<src.nocc[l], 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
+                k_m2m<<<src.nocc[l] * C, 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
                                                    pl.lev[l].mom);
     }
     {
@@ -1096,16 +1170,13 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
         if (bq.nm2m[t])
             kb_m2m<<<std::min(bq.nm2m[t], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.m2m[t], bq.nm2m[t], bq.M, t);
     for (int l = 2; l <= bq.maxd; ++l) {
+        if (bq.nl2l[l])
+            kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
         if (!bq.ns2l[l]) continue;
         switch (s2l_lb(bq.M)) {
         case 1: launch_s2l_batch<1, 8>(bq, l, st); break;
         case 2: launch_s2l_batch<2, 8>(bq, l, st); break;
-        case 3: launch_s2l_batch<3, 8>(bq, l, st); break;
-        case 4: launch_s2l_batch<4, 4>(bq, l, st); break;
-        case 5: launch_s2l_batch<5, 4>(bq, l, st); break;
-        case 6: launch_s2l_batch<6, 4>(bq, l, st); break;
-        case 7: launch_s2l_batch<7, 4>(bq, l, st); break;
-        default: launch_s2l_batch<8, 4>(bq, l, st); break;
+        default: launch_s2l_batch<3, 8>(bq, l, st); break;
         }
     }
     if (bq.nleaf) {

@@ -97,18 +97,24 @@ struct Side {
     int ntiles[AXF_MAX_DEPTH + 1] = {};
 };
 
-// Output-block width of the tiled S2L (smallest that fits the outputs of
-// one mode in a 64-lane wave) and boxes per tile.
+// Shape of the tiled S2L: output slots of one (box, channel) are rows k
+// split into blocks of LB columns; LB is the smallest width whose slots fit
+// in four waves, the block has one wave per 64 slots, and a tile holds TB
+// target boxes.
+inline int s2l_slots(int M, int lb)
+{
+    int s = 0;
+    for (int k = 0; k <= M; ++k) s += (M + 1 - k + lb - 1) / lb;
+    return s;
+}
 inline int s2l_lb(int M)
 {
-    for (int lb = 1; lb <= 8; ++lb) {
-        int s = 0;
-        for (int k = 0; k <= M; ++k) s += (M + 1 - k + lb - 1) / lb;
-        if (s <= 64) return lb;
-    }
-    return 8;
+    for (int lb = 1; lb <= 3; ++lb)
+        if (s2l_slots(M, lb) <= 256) return lb;
+    return 3;
 }
-inline int s2l_tb(int M) { return s2l_lb(M) <= 3 ? 8 : 4; }
+inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
+inline int s2l_tb(int) { return 8; }
 
 struct Level {
     int nb = 0;                // boxes per side, 2^l
@@ -213,13 +219,14 @@ struct ProbDev {
 
 // Merged work queues of a batch: one (problem, item) list per pass.
 // m2m[t] holds the step from level d-t+1 to d-t of each problem (so the
-// problems' different depths line up), s2l[l] the tiles x channels of level l.
+// problems' different depths line up), l2l[l] the target boxes x channels
+// and s2l[l] the tiles x channels of level l; p2m holds leaves x channels.
 struct BatchQueues {
     const ProbDev *probs = nullptr;
     int2 *gather = nullptr, *p2m = nullptr, *leaf = nullptr;
     int ngather = 0, np2m = 0, nleaf = 0;
-    int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *s2l[AXF_MAX_DEPTH + 1] = {};
-    int nm2m[AXF_MAX_DEPTH + 1] = {}, ns2l[AXF_MAX_DEPTH + 1] = {};
+    int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *s2l[AXF_MAX_DEPTH + 1] = {}, *l2l[AXF_MAX_DEPTH + 1] = {};
+    int nm2m[AXF_MAX_DEPTH + 1] = {}, ns2l[AXF_MAX_DEPTH + 1] = {}, nl2l[AXF_MAX_DEPTH + 1] = {};
     int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2;
     double chistar = 1e300;
 };

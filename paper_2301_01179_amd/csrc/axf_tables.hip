@@ -9,10 +9,11 @@
 // (r / h) and divided by h.  Starting values follow eq. gfunc:derivatives:x
 // and its r, r1 and mixed companions (the rational factors' x-derivatives are
 // taken from powers of w = x - i c, c = r +- r1); the remaining entries come
-// from the Laplace equation (eq. gfunc:laplace) by Leibniz' rule:
-//   (i+1)(i+2) g_{i+2,j,k} = sum_{u<=i} (-1)^u r^-(u+1) [(u+1) n^2/r g_{i-u,j,k}
-//                            - (i-u+1) g_{i-u+1,j,k}] - (k+1)(k+2) g_{i,j,k+2}
-// and its r <-> r1 image.  (The printed recursion lacks the last term.)
+// from the Laplace equation (eq. gfunc:laplace), here multiplied by r^2 so
+// that each entry needs five earlier ones (see k_tab_laplace), in r for the
+// columns b <= 1 and then in r1 for all a.  (The paper's form, divided by r,
+// is the Leibniz expansion of 1/r and 1/r^2; its printed version lacks the
+// axial term (k+1)(k+2) g_{i,j,k+2}.)
 #include <cmath>
 #include <vector>
 
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(256) void k_tab_laplace(int M, int nmodes, const Ge
                                                     double *__restrict__ tab)
 {
     extern __shared__ double t[];      // (M+1)^3 compact entries
-    __shared__ double ipr[AXF_MAX_ORDER + 2], ipr1[AXF_MAX_ORDER + 2], fact[2 * AXF_MAX_ORDER + 2];
+    __shared__ double fact[2 * AXF_MAX_ORDER + 2];
     const int K = 2 * M;
     const int g = blockIdx.x / nmodes, n = blockIdx.x - g * nmodes;
     const GeomDesc gd = geoms[g];
@@ -307,13 +308,6 @@ __global__ __launch_bounds__(256) void k_tab_laplace(int M, int nmodes, const Ge
     const double n2 = (double)n * n;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        double a = 1.0 / r, b = 1.0 / r1, pa = a, pb = b;
-        for (int u = 0; u <= M; ++u) {
-            ipr[u] = pa;
-            ipr1[u] = pb;
-            pa *= a;
-            pb *= b;
-        }
         double f = 1.0;
         for (int c = 0; c <= K; ++c) {
             fact[c] = f;
@@ -332,41 +326,43 @@ __global__ __launch_bounds__(256) void k_tab_laplace(int M, int nmodes, const Ge
         }
     }
     __syncthreads();
+    // The Laplace equation multiplied by r^2,
+    //   r^2 g_rr + r g_r - n^2 g + r^2 g_xx = 0,
+    // gives for the Taylor coefficients about r (rho = r' - r) a recursion of
+    // five terms (the form divided by r needs all previous rows):
+    //   r^2 (i+1)(i+2) g_(i+2) = -[ r (i+1)(2i+1) g_(i+1) + (i^2 - n^2) g_i
+    //                               + r^2 h_i + 2 r h_(i-1) + h_(i-2) ],
+    //   h_m = (k+1)(k+2) g_(m, k+2);  and the same in r1 for the source index.
     // r-recursion for b = 0, 1
     for (int i = 0; i + 2 <= M; ++i) {
-        int len0 = K - i - 2 + 1, len1 = K - i - 3 + 1;
-        const double inv = 1.0 / ((i + 1.0) * (i + 2.0));
+        const int len0 = K - i - 2 + 1, len1 = K - i - 3 + 1;
+        const double c1 = r * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
+        const double inv = -1.0 / (r * r * (i + 1.0) * (i + 2.0));
         for (int e = tid; e < len0 + len1; e += blockDim.x) {
-            int j = e < len0 ? 0 : 1, k = e < len0 ? e : e - len0;
-            double s = 0.0;
-            for (int u = 0; u <= i; ++u) {
-                double term = (u + 1) * n2 * ipr[0] * t[table_row(M, i - u, j) + k]
-                              - (i - u + 1) * t[table_row(M, i - u + 1, j) + k];
-                s += ((u & 1) ? -ipr[u] : ipr[u]) * term;
-            }
-            t[table_row(M, i + 2, j) + k] = s * inv - (k + 1.0) * (k + 2.0) * inv * t[table_row(M, i, j) + k + 2];
+            const int j = e < len0 ? 0 : 1, k = e < len0 ? e : e - len0;
+            const double kk = (k + 1.0) * (k + 2.0);
+            double v = c1 * t[table_row(M, i + 1, j) + k] + c0 * t[table_row(M, i, j) + k] +
+                       r * r * kk * t[table_row(M, i, j) + k + 2];
+            if (i >= 1) v += 2.0 * r * kk * t[table_row(M, i - 1, j) + k + 2];
+            if (i >= 2) v += kk * t[table_row(M, i - 2, j) + k + 2];
+            t[table_row(M, i + 2, j) + k] = v * inv;
         }
         __syncthreads();
     }
     // r1-recursion for all a
     for (int j = 0; j + 2 <= M; ++j) {
-        const double inv = 1.0 / ((j + 1.0) * (j + 2.0));
-        // items: a = 0..M, k = 0..K - a - j - 2
-        int tot = 0;
-        for (int a = 0; a <= M; ++a) tot += (K - a - j - 2 >= 0) ? (K - a - j - 1) : 0;
-        for (int e = tid; e < tot; e += blockDim.x) {
-            int a = 0, k = e;
-            while (k >= K - a - j - 1) {
-                k -= K - a - j - 1;
-                ++a;
-            }
-            double s = 0.0;
-            for (int u = 0; u <= j; ++u) {
-                double term = (u + 1) * n2 * ipr1[0] * t[table_row(M, a, j - u) + k]
-                              - (j - u + 1) * t[table_row(M, a, j - u + 1) + k];
-                s += ((u & 1) ? -ipr1[u] : ipr1[u]) * term;
-            }
-            t[table_row(M, a, j + 2) + k] = s * inv - (k + 1.0) * (k + 2.0) * inv * t[table_row(M, a, j) + k + 2];
+        const double c1 = r1 * (j + 1.0) * (2.0 * j + 1.0), c0 = (double)j * j - n2;
+        const double inv = -1.0 / (r1 * r1 * (j + 1.0) * (j + 2.0));
+        const int L0 = K - j - 1;                   // k range of a = 0
+        for (int e = tid; e < (M + 1) * L0; e += blockDim.x) {
+            const int a = e / L0, k = e - a * L0;
+            if (k > K - a - j - 2) continue;
+            const double kk = (k + 1.0) * (k + 2.0);
+            double v = c1 * t[table_row(M, a, j + 1) + k] + c0 * t[table_row(M, a, j) + k] +
+                       r1 * r1 * kk * t[table_row(M, a, j) + k + 2];
+            if (j >= 1) v += 2.0 * r1 * kk * t[table_row(M, a, j - 1) + k + 2];
+            if (j >= 2) v += kk * t[table_row(M, a, j - 2) + k + 2];
+            t[table_row(M, a, j + 2) + k] = v * inv;
         }
         __syncthreads();
     }

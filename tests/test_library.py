@@ -69,9 +69,12 @@ def test_null_and_size_errors():
 
 
 def test_mode_buckets_and_tile_widths_cover_limits():
-    """Host-side launch shapes (mirrors of the documented rules)."""
+    """Host-side launch shapes of the tiled S2L (mirror of the rule in the
+    library): up to the maximum order the output slots of one (box, channel)
+    fit in at most four waves with blocks of at most two columns."""
     import math
     for M in range(0, 25):
-        lb = next(b for b in range(1, 9)
-                  if sum(math.ceil((M + 1 - k) / b) for k in range(M + 1)) <= 64)
-        assert lb <= 7
+        lb = next(b for b in range(1, 4)
+                  if sum(math.ceil((M + 1 - k) / b) for k in range(M + 1)) <= 256)
+        slots = sum(math.ceil((M + 1 - k) / lb) for k in range(M + 1))
+        assert lb <= 2 and math.ceil(slots / 64) <= 4
