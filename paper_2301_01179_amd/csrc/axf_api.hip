@@ -175,6 +175,16 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     size_t ngeom = 12 * (((size_t)1 << (d + 1)) - 4);
     sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS);
     sz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+    // offset groups of the S2L pass and their partial-sum buffer (one level
+    // at a time, either side as targets)
+    size_t part = 0;
+    for (Side *sd : {&pl.src, &pl.fld})
+        for (int l = 2; l <= d; ++l) {
+            sd->s2l_groups[l] = s2l_group_count(sd->ntiles[l], pl.C, pl.M);
+            if (sd->s2l_groups[l] > 1)
+                part = std::max(part, (size_t)sd->s2l_groups[l] * sd->nocc[l] * pl.C * pl.P);
+        }
+    sz.add<double2>(std::max<size_t>(part, 1));
     pl.expn = arena_acquire(sz.bytes + 4096);
     for (int l = 2; l <= d; ++l) {
         size_t nb = (size_t)std::max(pl.src.nocc[l], pl.fld.nocc[l]);
@@ -187,6 +197,7 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     for (int l = 2; l <= d; ++l)
         pl.lev[l].tab = tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
     pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+    pl.s2l_part = pl.expn.take<double2>(std::max<size_t>(part, 1));
     build_tables(pl, st);
     pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes;
 }

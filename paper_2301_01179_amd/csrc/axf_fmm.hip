@@ -322,13 +322,15 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                                                  const int32_t *__restrict__ sslot,
                                                  const double2 *__restrict__ mom,
                                                  const double *__restrict__ tab,
-                                                 double2 *__restrict__ loc, int item)
+                                                 double2 *__restrict__ loc, int item, int G,
+                                                 double2 *__restrict__ part, int nocc)
 {
     extern __shared__ double2 ms[];          // [TB][P] staged moments
     __shared__ double invfact[AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
-    const int ti = item / C, c = item - (item / C) * C;
+    const int ti = item / (C * G), rem = item - ti * (C * G);
+    const int c = rem / G, g = rem - (rem / G) * G;    // channel, offset group
     const int n = c / nrhs;
     const int4 tl = tiles[ti];
     const int station = tl.x, nbx = tl.w;
@@ -369,11 +371,12 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
     const int par = tl.y;                       // z parity of the tile
     const int dr0 = -2 - (station & 1), dz0 = -2 - par;
     const double *tab_n = tab + (size_t)n * TS;
+    int oc = 0;                                 // index of the offset in the interaction list
     for (int dr = dr0; dr < dr0 + 6; ++dr) {
         const int jr = station + dr;
-        if (jr < 0 || jr >= nb) continue;
         for (int dz = dz0; dz < dz0 + 6; ++dz) {
             if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) continue;
+            if (oc++ % G != g || jr < 0 || jr >= nb) continue;   // another group's offset
             int ss[TB];
             bool any = false;
 #pragma unroll
@@ -417,23 +420,25 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                     const int a_ = outward ? k : i, b_ = outward ? i : k;
                     const double *row = T + table_row(M, a_, b_);
                     const int rl = 2 * M - a_ - b_;     // last valid c
-                    double w[LB];
-#pragma unroll
-                    for (int u = 0; u < LB; ++u) w[u] = row[min(l0 + u, rl)];
                     const int jn = M - i;
-                    for (int j = 0; j <= jn; ++j) {
+                    // the lane's whole window for this i: all loads in flight at once
+                    constexpr int NW = AXF_MAX_ORDER + LB;
+                    double w[NW];
 #pragma unroll
-                        for (int b = 0; b < TB; ++b) {
-                            const double2 sv = ms[b * P + pbase + j];
+                    for (int q = 0; q < NW; ++q) w[q] = (q < jn + LB) ? row[min(l0 + q, rl)] : 0.0;
 #pragma unroll
-                            for (int u = 0; u < LB; ++u) {
-                                acc[u][b].x = fma(w[u], sv.x, acc[u][b].x);
-                                acc[u][b].y = fma(w[u], sv.y, acc[u][b].y);
+                    for (int j = 0; j <= AXF_MAX_ORDER; ++j) {
+                        if (j <= jn) {
+#pragma unroll
+                            for (int b = 0; b < TB; ++b) {
+                                const double2 sv = ms[b * P + pbase + j];
+#pragma unroll
+                                for (int u = 0; u < LB; ++u) {
+                                    acc[u][b].x = fma(w[j + u], sv.x, acc[u][b].x);
+                                    acc[u][b].y = fma(w[j + u], sv.y, acc[u][b].y);
+                                }
                             }
                         }
-#pragma unroll
-                        for (int u = 0; u + 1 < LB; ++u) w[u] = w[u + 1];
-                        w[LB - 1] = row[min(j + 1 + l0 + LB - 1, rl)];
                     }
                     pbase += jn + 1;
                 }
@@ -448,7 +453,8 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
         }
     }
     __syncthreads();                            // invfact is visible even when no offset ran
-    // add (-1)^l / l! * acc to the locals (each output has exactly one owner)
+    // (-1)^l / l! * acc: added to the locals, or this group's partial sums
+    // (each output has exactly one owner in a block)
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
         if (!live || sl[b] < 0) continue;
@@ -457,13 +463,33 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
             const int ll = l0 + u;
             if (ll > M - k) continue;
             const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
-            double2 *o = loc + ((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll);
-            double2 v = *o;
-            v.x = fma(f, acc[u][b].x, v.x);
-            v.y = fma(f, acc[u][b].y, v.y);
-            *o = v;
+            const int64_t e = ((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll);
+            if (part) {
+                part[(int64_t)g * nocc * C * P + e] = make_double2(f * acc[u][b].x, f * acc[u][b].y);
+            } else {
+                double2 v = loc[e];
+                v.x = fma(f, acc[u][b].x, v.x);
+                v.y = fma(f, acc[u][b].y, v.y);
+                loc[e] = v;
+            }
         }
     }
+}
+
+// Sum of the offset groups' partial S2L results into the locals, in group
+// order (deterministic).
+__global__ __launch_bounds__(256) void k_s2l_reduce(int64_t n, int G, const double2 *__restrict__ part,
+                                                   double2 *__restrict__ loc)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double2 v = loc[e];
+    for (int g = 0; g < G; ++g) {
+        const double2 x = part[(int64_t)g * n + e];
+        v.x += x.x;
+        v.y += x.y;
+    }
+    loc[e] = v;
 }
 
 template <int LB, int TB>
@@ -471,9 +497,11 @@ __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, i
                                                   const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
                                                   const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
                                                   const double2 *__restrict__ mom, const double *__restrict__ tab,
-                                                  double2 *__restrict__ loc)
+                                                  double2 *__restrict__ loc, int G, double2 *__restrict__ part,
+                                                  int nocc)
 {
-    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x);
+    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
+                          part, nocc);
 }
 
 // ------------------------------------------------------------ pair sums
@@ -924,9 +952,15 @@ template <int LB, int TB>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     size_t shm = sizeof(double2) * (size_t)TB * pl.P;
-    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C, 64 * s2l_waves(pl.M), shm, st>>>(
+    const int G = tgt.s2l_groups[l];
+    double2 *part = G > 1 ? pl.s2l_part : nullptr;
+    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
         pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],
-        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc);
+        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l]);
+    if (G > 1) {
+        const int64_t n = (int64_t)tgt.nocc[l] * pl.C * pl.P;
+        k_s2l_reduce<<<(int)((n + 255) / 256), 256, 0, st>>>(n, G, part, pl.lev[l].loc);
+    }
 }
 
 void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
@@ -1038,7 +1072,7 @@ __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, con
         const ProbDev &pd = P[it.x];
         __syncthreads();
         s2l_tile_body<LB, TB>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
-                              pd.mom[l], pd.tab[l], pd.loc[l], it.y);
+                              pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0);
     }
 }
 

@@ -95,6 +95,7 @@ struct Side {
     int4 *tiles[AXF_MAX_DEPTH + 1] = {};
     int32_t *tile_slots[AXF_MAX_DEPTH + 1] = {};
     int ntiles[AXF_MAX_DEPTH + 1] = {};
+    int s2l_groups[AXF_MAX_DEPTH + 1] = {};  // offset groups of the S2L pass at each level
 };
 
 // Shape of the tiled S2L: output slots of one (box, channel) are rows k
@@ -115,6 +116,15 @@ inline int s2l_lb(int M)
 }
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
 inline int s2l_tb(int) { return 8; }
+// Offset groups of a level: the 27 interaction-list offsets of a (tile,
+// channel) are split over G blocks so that a level launches ~2048 waves.
+inline int s2l_group_count(int ntiles, int C, int M)
+{
+    const int64_t waves = (int64_t)ntiles * C * s2l_waves(M);
+    if (waves <= 0) return 1;
+    int64_t g = (2048 + waves - 1) / waves;
+    return (int)(g < 1 ? 1 : g > 9 ? 9 : g);
+}
 
 struct Level {
     int nb = 0;                // boxes per side, 2^l
@@ -144,6 +154,7 @@ struct Plan {
     Side src, fld;
     Level lev[AXF_MAX_DEPTH + 1];
     double2 *Sg = nullptr;      // gathered strengths, point-major [max(ns, nf)][Cs]
+    double2 *s2l_part = nullptr;  // partial S2L sums of the offset groups of one level
     double *gsum = nullptr;     // adjoint coordinate-gradient scratch
     double *tab_scratch = nullptr;
     Arena points, tree, expn, tilemem;
