@@ -43,13 +43,16 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
-// Forward-recursion limit: rounding grows like lambda^(2N), lambda = chi +
-// sqrt(chi^2 - 1); below chi* the growth stays under ~100.
+// Forward-recursion limit.  Rounding in the forward recursion grows like
+// lambda^(2n), lambda = chi + sqrt(chi^2 - 1) = e^eta, relative to G^(n).
+// The paper's switch chi* = 1.008 for modes up to N = 32 (App. A) allows
+// growth e^(2 N eta) = e^(64 acosh 1.008) ~ 3300 at the top mode; the same
+// bound is used for every N: eta* = 32 acosh(1.008) / N.
 inline double forward_chi_limit(int nmodes)
 {
     int N = nmodes - 1;
     if (N < 2) return 1e300;
-    double eta = 4.605170185988091 / (2.0 * N);   // ln(100) / (2N)
+    const double eta = 32.0 * __builtin_acosh(1.008) / N;
     return 0.5 * (__builtin_exp(eta) + __builtin_exp(-eta));
 }
 

@@ -547,6 +547,9 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
     }
     const bool back = (NMB > 2) && ps.chi >= chistar;
     const bool anyback = __ballot(back) != 0;
+    // every pair of the wave on the backward branch (idle lanes have g0 = 0
+    // and contribute nothing either way): no forward recursion needed
+    const bool allback = anyback && __ballot(use && !back) == 0;
     double scale = 0.0;
     if constexpr (NMB > 2) {
         if (anyback) {
@@ -619,14 +622,15 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
         iprm = fast_rcp(rm2);
         Ar = (r * r - r1 * r1 - x * x) * 0.5 * inv_r;
         hr = -0.5 * inv_r;
-        if (anyback && back) gprev = scale * lg[1 * 64 + lane];
+        if (anyback && (back || allback)) gprev = scale * lg[1 * 64 + lane];
     }
 #pragma unroll
     for (int n = 0; n < NMB; ++n) {
         {
             double g = gcur;
             if constexpr (NMB > 2) {
-                if (anyback) g = back ? scale * lg[n * 64 + lane] : g;
+                if (allback) g = scale * lg[n * 64 + lane];
+                else if (anyback) g = back ? scale * lg[n * 64 + lane] : g;
             }
             const double2 v = Ss[n];
             A.ar[n] = fma(g, v.x, A.ar[n]);
@@ -645,7 +649,7 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
             // bound the scheduling window: keeps only a few modes' loads in flight
             if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
             // forward recursion for the next mode
-            if (n + 1 < NMB) {
+            if (n + 1 < NMB && !allback) {
                 double gn;
                 if (n == 0) {
                     gn = ps.g1;
