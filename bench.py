@@ -251,6 +251,9 @@ def main():
                                                 args.steps, args.warmup)
     info = plan.info()
     work = plan.work()
+    census = plan.census()["near"]
+    P_ = (args.order + 1) * (args.order + 2) / 2
+    local_eval_flops = nf * (4.0 * P_ * nm + 2.0 * P_)        # local expansions at the field points
 
     # GPU direct sum (same points) for the speed-up
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -340,6 +343,10 @@ def main():
         "fmm_vs_direct_speedup": t_direct / t_step,
         "fmm_vs_direct_speedup_eval_only": t_direct / t_eval,
         "near_pairs": work["near_pairs"], "s2l_box_pairs": work["s2l_pairs"],
+        "near_census": {"backward_fraction": census["backward"] / max(census["pairs"], 1.0),
+                        "agm_iterations_per_pair": census["agm_iterations"] / max(census["pairs"], 1.0),
+                        "recursion_steps_per_pair": census["steps"] / max(census["pairs"], 1.0),
+                        "model_flops_per_pair": (work["flops"]["leaf"] - local_eval_flops) / max(census["pairs"], 1.0)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "config_order_result": secondary,

@@ -173,11 +173,25 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHAS
                                 int32_t *launches /* host [AXF_NUM_PHASES] */);
 
 /* Algorithmic work of one evaluation (host outputs, any may be NULL):
- * near-field ring pairs, S2L box pairs, and the floating-point operation
- * counts of the model documented with the benchmark (FP64 flops per phase,
- * [AXF_NUM_PHASES]). */
+ * near-field ring pairs, S2L box pairs, and FP64 operation counts per phase
+ * ([AXF_NUM_PHASES], fma = 2).  Pair sums: 21 flops per pair + 9 per AGM
+ * iteration + 3 per recursion step + (N + 6) per pair on the backward branch
+ * + 4 per mode and right-hand side, with the iteration and step counts each
+ * pair needs taken from a census of the plan's pairs (sampled to about 3e7
+ * pairs for the direct sum); P2M 4 P C + 2 P per source; separable M2M
+ * 24 C(M+3, 3) per parent box and channel, L2L 8 C(M+3, 3) per box and
+ * channel; S2L 4 P^2 per box pair and channel; local
+ * evaluation 4 P C + 2 P per field point.  The census runs once, on the
+ * first call that asks for flops, and synchronises the device. */
 axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs,
                          double *flops /* host [AXF_NUM_PHASES] */);
+
+/* The pair census behind the flop model (host outputs, either may be NULL):
+ * [pairs, backward-branch pairs, AGM iterations, recursion steps] summed over
+ * the near-field pairs, and the same for the direct sum (sampled and
+ * scaled).  Runs the census on first use; synchronises the device. */
+axf_status axf_plan_census(const axf_plan *plan, double *near_counts /* [4] */,
+                           double *direct_counts /* [4] */);
 
 /* ---------------------------------------------------------------------- */
 /* Batched launches: many independent problems (uneven sizes, own points,

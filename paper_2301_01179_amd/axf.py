@@ -25,6 +25,7 @@ EXPORTED = [
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
     "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
     "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
+    "axf_plan_census",
 ]
 
 PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct"]
@@ -87,10 +88,12 @@ def load_library(path: str = LIB_PATH):
     lib.axf_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i32)]
     lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(ctypes.c_double)]
     lib.axf_plan_table.argtypes = [vp, i32, i32, i32, i32, P(ctypes.c_double)]
+    lib.axf_plan_census.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double)]
     for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
                  "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
-                 "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table"):
+                 "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
+                 "axf_plan_census"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -189,6 +192,14 @@ class Plan:
         _check(_lib.axf_plan_work(self._h, ctypes.byref(near), ctypes.byref(s2l), fl), "axf_plan_work")
         return {"near_pairs": near.value, "s2l_pairs": s2l.value,
                 "flops": {p: fl[i] for i, p in enumerate(PHASES)}}
+
+    def census(self) -> dict:
+        """Pair census behind the flop model: near field and direct sum,
+        each {pairs, backward, agm_iterations, steps}."""
+        a, b = (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
+        _check(_lib.axf_plan_census(self._h, a, b), "axf_plan_census")
+        keys = ("pairs", "backward", "agm_iterations", "steps")
+        return {"near": dict(zip(keys, list(a))), "direct": dict(zip(keys, list(b)))}
 
     def table(self, level: int, station: int, dr: int, dz: int):
         """The stored S2L table of (level, inner station, separation) as a

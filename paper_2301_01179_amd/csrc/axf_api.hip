@@ -411,28 +411,56 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
 {
     AXF_TRY({
         AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
-        const Plan &pl = plan->pl;
+        Plan &pl = const_cast<axf_plan *>(plan)->pl;
         if (near_pairs) *near_pairs = pl.near_pairs;
         if (s2l_pairs) *s2l_pairs = pl.s2l_pairs;
         if (flops) {
-            // FP64 operation model (fma = 2): a near-field pair costs a fixed
-            // 60 flops of geometry and AGM, 3 per mode of recursion and 4 per
-            // mode and right-hand side of complex accumulation.
-            const double P = pl.P, C = pl.C, Nm = pl.nmodes, R = pl.nrhs;
-            const double M = pl.M;
-            const double c4 = (M + 1) * (M + 2) * (M + 3) * (M + 4) / 24.0;   // C(M+4, 4)
-            double pair = 60.0 + 3.0 * Nm + 4.0 * Nm * R;
-            double nbox_up = 0, nbox_down = 0;
-            for (int l = 3; l <= pl.d; ++l) {
-                nbox_up += pl.src.nocc[l];
-                nbox_down += pl.fld.nocc[l];
+            if (!pl.census_done) {
+                AXF_HIP(hipSetDevice(pl.device));
+                pair_census(pl, false, pl.census_near, nullptr);
+                pair_census(pl, true, pl.census_direct, nullptr);
+                pl.census_done = true;
             }
+            // FP64 operation model (fma = 2).  A pair costs 21 flops of
+            // geometry, start values and chi, 9 per AGM iteration, 3 per
+            // recursion step, N + 6 more on the backward branch (asymptotic
+            // start and normalisation) and 4 per mode and right-hand side of
+            // complex accumulation; iteration and step counts come from the
+            // pair census (what each pair needs, not what a wave executes).
+            const double P = pl.P, C = pl.C, Nm = pl.nmodes, R = pl.nrhs, N = pl.N;
+            const double M = pl.M;
+            const double c3 = (M + 1) * (M + 2) * (M + 3) / 6.0;   // C(M+3, 3): one separable pass
+            auto pair_flops = [&](const double *cs) {
+                return cs[0] * (21.0 + 4.0 * Nm * R) + 9.0 * cs[2] + 3.0 * cs[3] + cs[1] * (N + 6.0);
+            };
+            double nbox_up = 0, nbox_down = 0;   // M2M parents, L2L children
+            for (int l = 2; l < pl.d; ++l) nbox_up += pl.src.nocc[l];
+            for (int l = 3; l <= pl.d; ++l) nbox_down += pl.fld.nocc[l];
             flops[AXF_PHASE_GATHER] = 0.0;
             flops[AXF_PHASE_P2M] = (double)pl.src.n * (4.0 * P * C + 2.0 * P);
-            flops[AXF_PHASE_M2M] = nbox_up * C * c4 * 4.0;
-            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0 + nbox_down * C * c4 * 4.0;
-            flops[AXF_PHASE_LEAF] = (double)pl.near_pairs * pair + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
-            flops[AXF_PHASE_DIRECT] = (double)pl.src.n * (double)pl.fld.n * pair;
+            // separable shifts: M2M 4 children in z + 2 parities in r, L2L r then z
+            flops[AXF_PHASE_M2M] = nbox_up * C * c3 * 24.0;
+            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0 + nbox_down * C * c3 * 8.0;
+            flops[AXF_PHASE_LEAF] = pair_flops(pl.census_near) + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
+            flops[AXF_PHASE_DIRECT] = pair_flops(pl.census_direct);
+        }
+    })
+}
+
+axf_status axf_plan_census(const axf_plan *plan, double *near_counts, double *direct_counts)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
+        Plan &pl = const_cast<axf_plan *>(plan)->pl;
+        if (!pl.census_done) {
+            AXF_HIP(hipSetDevice(pl.device));
+            pair_census(pl, false, pl.census_near, nullptr);
+            pair_census(pl, true, pl.census_direct, nullptr);
+            pl.census_done = true;
+        }
+        for (int q = 0; q < 4; ++q) {
+            if (near_counts) near_counts[q] = pl.census_near[q];
+            if (direct_counts) direct_counts[q] = pl.census_direct[q];
         }
     })
 }

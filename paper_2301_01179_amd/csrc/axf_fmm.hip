@@ -1131,6 +1131,87 @@ void launch_leaf_batch(const BatchQueues &bq, hipStream_t st)
     kb_leaf<NMB><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes, bq.chistar);
 }
 
+// ------------------------------------------------------------- census
+// Work census of the pair sums for the flop model: per pair, the AGM
+// iterations to convergence (the criterion of pair_start) and the recursion
+// steps the pair itself needs (forward: N - 1; backward: N + 3 +
+// 12 / sqrt(2 (chi - 1)), the count the backward branch uses for its worst
+// lane).  Sums per block: [pairs, backward pairs, AGM iterations, steps].
+__device__ __forceinline__ void census_pair(double r, double z, double r1, double z1, double chistar, int N,
+                                            double (&cnt)[4])
+{
+    if (r == r1 && z == z1) return;
+    const double x = z - z1, dr = r - r1, sr = r + r1;
+    const double rm2 = dr * dr + x * x, rp2 = sr * sr + x * x, rr = r * r1;
+    double a = sqrt(rp2), b = sqrt(rm2), c = 2.0 * rr / (a + b);
+    int it = 0;
+    for (; it < 48;) {
+        const double an = 0.5 * (a + b);
+        b = sqrt(a * b);
+        a = an;
+        ++it;
+        if (c <= 0x1p-30 * a) break;
+        c = 0.5 * (a - b);
+    }
+    const double dchi = rm2 / (2.0 * rr);
+    cnt[0] += 1.0;
+    cnt[2] += it;
+    if (1.0 + dchi >= chistar) {
+        cnt[1] += 1.0;
+        cnt[3] += N + 3 + ceil(12.0 / sqrt(2.0 * dchi));
+    } else {
+        cnt[3] += N > 1 ? N - 1 : 0;
+    }
+}
+
+__device__ __forceinline__ void census_block_sum(double (&cnt)[4], double *__restrict__ out)
+{
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = cnt[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) v += red[threadIdx.x][t];
+        out[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+}
+
+// near field: one thread per target of a leaf chunk, the sources of the 3x3
+// neighbour leaves
+__global__ __launch_bounds__(64) void k_census_near(int depth, int N, double chistar,
+                                                   const int4 *__restrict__ chunks, SideView tv, SideView sv,
+                                                   double *__restrict__ out)
+{
+    const int4 ch = chunks[blockIdx.x];
+    double cnt[4] = {0.0, 0.0, 0.0, 0.0};
+    if ((int)threadIdx.x < ch.z) {
+        const int t = ch.y + threadIdx.x;
+        const double r = tv.r[t], z = tv.z[t];
+        const int nb = 1 << depth;
+        const int ir = ch.w / nb, iz = ch.w - (ch.w / nb) * nb;
+        for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
+            for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) {
+                const uint32_t m = morton((uint32_t)jr, (uint32_t)jz);
+                for (int s = sv.off[m]; s < sv.off[m + 1]; ++s) census_pair(r, z, sv.r[s], sv.z[s], chistar, N, cnt);
+            }
+    }
+    census_block_sum(cnt, out);
+}
+
+// direct sum: every `stride`-th target against all sources
+__global__ __launch_bounds__(256) void k_census_direct(int N, double chistar, SideView tv, int64_t nt, int64_t stride,
+                                                      SideView sv, int64_t ns, double *__restrict__ out)
+{
+    double cnt[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * stride;
+    if (t < nt) {
+        const double r = tv.r[t], z = tv.z[t];
+        for (int64_t s = 0; s < ns; ++s) census_pair(r, z, sv.r[s], sv.z[s], chistar, N, cnt);
+    }
+    census_block_sum(cnt, out);
+}
+
 #define AXF_BUCKETS(X) X(4) X(9) X(12) X(17) X(24) X(33) X(48) X(64)
 
 }  // namespace
@@ -1260,4 +1341,43 @@ void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd)
     pd.chunks = pl.fld.chunks;
 }
 
+void pair_census(Plan &pl, bool direct, double out[4], hipStream_t st)
+{
+    const Side &src = pl.src, &tgt = pl.fld;
+    int nblk;
+    int64_t stride = 1;
+    if (direct) {
+        // sample targets so that about 3e7 pairs are visited
+        stride = std::max<int64_t>(1, (int64_t)((double)tgt.n * src.n / 3e7));
+        const int64_t nsamp = (tgt.n + stride - 1) / stride;
+        nblk = (int)((nsamp + 255) / 256);
+    } else {
+        nblk = tgt.nchunks;
+    }
+    for (int q = 0; q < 4; ++q) out[q] = 0.0;
+    if (nblk == 0) return;
+    double *d = nullptr;
+    AXF_HIP(hipMalloc(&d, sizeof(double) * 4 * (size_t)nblk));
+    if (direct)
+        k_census_direct<<<nblk, 256, 0, st>>>(pl.N, pl.chistar, view_of(tgt), tgt.n, stride, view_of(src), src.n, d);
+    else
+        k_census_near<<<nblk, 64, 0, st>>>(pl.d, pl.N, pl.chistar, tgt.chunks, view_of(tgt), view_of(src), d);
+    std::vector<double> h(4 * (size_t)nblk);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st);
+    hipError_t e3 = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    AXF_HIP(e1);
+    AXF_HIP(e2);
+    AXF_HIP(e3);
+    for (int b = 0; b < nblk; ++b)
+        for (int q = 0; q < 4; ++q) out[q] += h[4 * (size_t)b + q];
+    if (direct) {
+        // scale the sampled counts to all targets
+        const double f = (double)tgt.n / (double)((tgt.n + stride - 1) / stride);
+        for (int q = 0; q < 4; ++q) out[q] *= f;
+    }
+}
+
 }  // namespace axf
+

@@ -159,6 +159,8 @@ struct Plan {
     double *tab_scratch = nullptr;
     Arena points, tree, expn, tilemem;
     int64_t near_pairs = 0, s2l_pairs = 0;
+    bool census_done = false;
+    double census_near[4] = {}, census_direct[4] = {};
     size_t device_bytes = 0;
     // phase timing (HIP events on the evaluation stream)
     bool timing = false;
@@ -242,6 +244,9 @@ struct BatchQueues {
     double chistar = 1e300;
 };
 void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd);
+// Pair census of the near field (or, sampled, of the direct sum) with the
+// field points as targets: [pairs, backward pairs, AGM iterations, steps].
+void pair_census(Plan &pl, bool direct, double out[4], hipStream_t st);
 void run_batch(const BatchQueues &bq, hipStream_t st);
 
 }  // namespace axf

@@ -1,0 +1,66 @@
+"""The pair census behind the flop model (marked gpu), against a numpy count
+on the same tree: near-field pairs (sources in the 3 x 3 neighbour leaves of
+each field point's leaf, coincident points excluded), pairs on the backward
+branch (chi >= chi*, chi* = cosh(32 acosh(1.008) / N)), AGM iterations to
+the convergence criterion c <= 2^-30 a, and recursion steps per pair
+(N - 1 forward; N + 3 + ceil(12 / sqrt(2 (chi - 1))) backward)."""
+import math
+
+import numpy as np
+
+from gpu_util import gpu, need_gpu
+from oracle import oracle as O
+from paper_2301_01179_amd import inputs
+
+
+def _expected(rs, zs, rf, zf, depth, nmodes):
+    N = nmodes - 1
+    chistar = math.cosh(32.0 * math.acosh(1.008) / N) if N >= 2 else 1e300
+    rlo, zlo, L, invL = O.square_info(rs, zs, rf, zf)
+    isr, isz = O.box_indices(rs, zs, rlo, zlo, invL, depth)
+    ifr, ifz = O.box_indices(rf, zf, rlo, zlo, invL, depth)
+    cnt = np.zeros(4)
+    for t in range(rf.size):
+        near = (np.abs(isr - ifr[t]) <= 1) & (np.abs(isz - ifz[t]) <= 1)
+        r1, z1 = rs[near], zs[near]
+        keep = ~((r1 == rf[t]) & (z1 == zf[t]))
+        r1, z1 = r1[keep], z1[keep]
+        r, x = rf[t], zf[t] - z1
+        rm2 = (r - r1) ** 2 + x * x
+        rp2 = (r + r1) ** 2 + x * x
+        rr = r * r1
+        a, b = np.sqrt(rp2), np.sqrt(rm2)
+        c = 2.0 * rr / (a + b)
+        it = np.zeros(r1.size)
+        done = np.zeros(r1.size, dtype=bool)
+        for _ in range(48):
+            an = 0.5 * (a + b)
+            b = np.where(done, b, np.sqrt(a * b))
+            a = np.where(done, a, an)
+            it += ~done
+            done |= c <= 2.0 ** -30 * a
+            c = np.where(done, c, 0.5 * (a - b))
+            if done.all():
+                break
+        dchi = rm2 / (2.0 * rr)
+        back = 1.0 + dchi >= chistar
+        steps = np.where(back, N + 3 + np.ceil(12.0 / np.sqrt(2.0 * dchi)), max(N - 1, 0))
+        cnt += [r1.size, back.sum(), it.sum(), steps.sum()]
+    return cnt
+
+
+@gpu
+def test_census_matches_numpy_count():
+    need_gpu()
+    from paper_2301_01179_amd import axf
+    rs, zs, rf, zf, _ = inputs.annulus(1500, 700, 17, seed=9)
+    plan = axf.Plan(rs, zs, rf, zf, 17, 8, depth=3)
+    got = plan.census()["near"]
+    ref = _expected(rs, zs, rf, zf, 3, 17)
+    assert got["pairs"] == ref[0] == plan.work()["near_pairs"]
+    assert got["backward"] == ref[1]
+    # AGM iteration counts can differ by one where c sits at the threshold
+    assert abs(got["agm_iterations"] - ref[2]) <= 1e-3 * ref[2]
+    assert abs(got["steps"] - ref[3]) <= 1e-3 * ref[3]
+    d = plan.census()["direct"]
+    assert d["pairs"] == 1500 * 700 - np.sum((rs[:, None] == rf[None, :]) & (zs[:, None] == zf[None, :]))
