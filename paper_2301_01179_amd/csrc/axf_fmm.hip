@@ -521,13 +521,59 @@ struct Acc {
     }
 };
 
+// Backward-branch values of a pair: in registers for the potential-only
+// kernels of up to 24 modes, otherwise in the wave's LDS scratch `lg`
+// [NMB][64] (the gradient accumulators leave no registers for them).
+template <int NMB, int MODE>
+struct BackVals {
+    static constexpr bool kReg = MODE == 0 && NMB <= 24;
+    double v[kReg ? NMB : 1];
+    double *lg;
+    int lane;
+    __device__ __forceinline__ void set(int n, double x)
+    {
+        if constexpr (kReg) v[n] = x;
+        else lg[n * 64 + lane] = x;
+    }
+    __device__ __forceinline__ double get(int n) const
+    {
+        if constexpr (kReg) return v[n];
+        else return lg[n * 64 + lane];
+    }
+};
+
+// One mode's contribution g = G^(n) of a pair: potential, and for MODE != 0
+// the r- and x-derivatives from G^(n) and G^(n-1) (App. A, first-derivative
+// starting formulas).
+struct PairDeriv {
+    double iprp, iprm, Ar, hr, x;
+};
+template <int NMB, int MODE>
+__device__ __forceinline__ void accum_mode(Acc<NMB, MODE> &A, int n, double g, double &gprev, const double2 v,
+                                           const PairDeriv &pd)
+{
+    A.ar[n] = fma(g, v.x, A.ar[n]);
+    A.ai[n] = fma(g, v.y, A.ai[n]);
+    if constexpr (MODE != 0) {
+        const double nu = n - 0.5;
+        const double W = (g + gprev) * pd.iprp + (g - gprev) * pd.iprm;
+        const double gdr = fma(pd.hr, g, nu * pd.Ar * W);
+        const double gdx = nu * pd.x * W;
+        A.rr_[n] = fma(gdr, v.x, A.rr_[n]);
+        A.ri_[n] = fma(gdr, v.y, A.ri_[n]);
+        A.zr_[n] = fma(gdx, v.x, A.zr_[n]);
+        A.zi_[n] = fma(gdx, v.y, A.zi_[n]);
+        gprev = g;
+    }
+}
+
 // Adds S_s^(n) G^(n)(r, r1, x) for n < nmodes of one pair per lane.  All
 // lanes of the wave call it together (the backward recursion runs a
 // wave-wide number of steps).  `use` = false lanes contribute nothing.
-// Forward recursion (chi < chistar) streams straight into the accumulators;
-// backward (Miller) values go through `lg`, this wave's LDS scratch
-// [NMB][64].  Ss points at the source's strengths of modes 0..NMB-1 for this
-// right-hand side (zero beyond nmodes).
+// The wave takes one of three mode streams: all pairs forward (recursion
+// streams into the accumulators), all backward (normalised Miller values),
+// or mixed (both, selected per lane).  Ss points at the source's strengths
+// of modes 0..NMB-1 for this right-hand side (zero beyond nmodes).
 template <int NMB, int MODE>
 __device__ __forceinline__ void pair_accum(double r, double r1, double x, double inv_r, double inv_r1, bool use,
                                            double chistar, int nmodes, const double2 *Ss,
@@ -550,7 +596,9 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
     // every pair of the wave on the backward branch (idle lanes have g0 = 0
     // and contribute nothing either way): no forward recursion needed
     const bool allback = anyback && __ballot(use && !back) == 0;
-    double scale = 0.0;
+    BackVals<NMB, MODE> bv;
+    bv.lg = lg;
+    bv.lane = lane;
     if constexpr (NMB > 2) {
         if (anyback) {
             // Miller's backward recursion, started from the large-n limit of
@@ -598,7 +646,7 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
             if (e > emax) e = emax;
             y = ldexp(y, -e);
             yp = ldexp(yp, -e);
-            lg[(NMB - 1) * 64 + lane] = y;
+            bv.set(NMB - 1, y);
             double up = yp;
 #pragma unroll
             for (int n = NMB - 1; n >= 1; --n) {
@@ -606,60 +654,58 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
                 double ym = fma(fa * chi, y, -fb * up);
                 up = y;
                 y = ym;
-                lg[(n - 1) * 64 + lane] = y;
+                bv.set(n - 1, y);
             }
-            scale = ps.g0 * fast_rcp(y);
+            // normalise by G^(0) from the AGM
+            const double scale = ps.g0 * fast_rcp(y);
+#pragma unroll
+            for (int n = 0; n < NMB; ++n) bv.set(n, scale * bv.get(n));
         }
     }
-    // stream over modes
-    const double chi = ps.chi;
-    double gprev = ps.g1;       // G^(n-1), with G^(-1) = G^(1)
-    double gcur = ps.g0;        // forward value of G^(n)
-    double gnext = ps.g1;
-    double iprp = 0.0, iprm = 0.0, Ar = 0.0, hr = 0.0;
+    PairDeriv pd{};
     if constexpr (MODE != 0) {
-        iprp = fast_rcp(rp2);
-        iprm = fast_rcp(rm2);
-        Ar = (r * r - r1 * r1 - x * x) * 0.5 * inv_r;
-        hr = -0.5 * inv_r;
-        if (anyback && (back || allback)) gprev = scale * lg[1 * 64 + lane];
+        pd.iprp = fast_rcp(rp2);
+        pd.iprm = fast_rcp(rm2);
+        pd.Ar = (r * r - r1 * r1 - x * x) * 0.5 * inv_r;
+        pd.hr = -0.5 * inv_r;
+        pd.x = x;
     }
+    const double chi = ps.chi;
+    if (MODE == 0 && NMB > 2 && allback) {
+        double gprev = bv.get(1);               // G^(-1) = G^(1)
+#pragma unroll
+        for (int n = 0; n < NMB; ++n) {
+            accum_mode<NMB, MODE>(A, n, bv.get(n), gprev, Ss[n], pd);
+            if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    }
+    // forward recursion streamed over the modes (mixed waves select the
+    // backward value on their backward lanes)
+    double gprev = ps.g1;
+    if constexpr (MODE != 0 && NMB > 2) {
+        if (anyback && back) gprev = bv.get(1);
+    }
+    double gcur = ps.g0, gnext = ps.g1;
 #pragma unroll
     for (int n = 0; n < NMB; ++n) {
-        {
-            double g = gcur;
-            if constexpr (NMB > 2) {
-                if (allback) g = scale * lg[n * 64 + lane];
-                else if (anyback) g = back ? scale * lg[n * 64 + lane] : g;
+        double g = gcur;
+        if constexpr (NMB > 2) {
+            if (anyback) g = back ? bv.get(n) : g;
+        }
+        accum_mode<NMB, MODE>(A, n, g, gprev, Ss[n], pd);
+        // bound the scheduling window: keeps only a few modes' loads in flight
+        if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        if (n + 1 < NMB) {
+            double gn;
+            if (n == 0) {
+                gn = ps.g1;
+            } else {
+                const double fa = 4.0 * n / (2.0 * n + 1.0), fb = (2.0 * n - 1.0) / (2.0 * n + 1.0);
+                gn = fma(fa * chi, gcur, -fb * gnext);
             }
-            const double2 v = Ss[n];
-            A.ar[n] = fma(g, v.x, A.ar[n]);
-            A.ai[n] = fma(g, v.y, A.ai[n]);
-            if constexpr (MODE != 0) {
-                const double nu = n - 0.5;
-                const double W = (g + gprev) * iprp + (g - gprev) * iprm;
-                const double gdr = fma(hr, g, nu * Ar * W);
-                const double gdx = nu * x * W;
-                A.rr_[n] = fma(gdr, v.x, A.rr_[n]);
-                A.ri_[n] = fma(gdr, v.y, A.ri_[n]);
-                A.zr_[n] = fma(gdx, v.x, A.zr_[n]);
-                A.zi_[n] = fma(gdx, v.y, A.zi_[n]);
-                gprev = g;
-            }
-            // bound the scheduling window: keeps only a few modes' loads in flight
-            if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-            // forward recursion for the next mode
-            if (n + 1 < NMB && !allback) {
-                double gn;
-                if (n == 0) {
-                    gn = ps.g1;
-                } else {
-                    const double fa = 4.0 * n / (2.0 * n + 1.0), fb = (2.0 * n - 1.0) / (2.0 * n + 1.0);
-                    gn = fma(fa * chi, gcur, -fb * gnext);
-                }
-                gnext = gcur;   // holds G^(n) for the next step's G^(n-1)
-                gcur = gn;
-            }
+            gnext = gcur;   // holds G^(n) for the next step's G^(n-1)
+            gcur = gn;
         }
     }
 }
