@@ -294,19 +294,40 @@ size_t start_lds_bytes(int M, int nmodes)
     return sizeof(dd) * (size_t)(2 * M + 1) * (10 + 2 * (Nw + 1));
 }
 
-// Laplace recursion for one (geometry, mode) in LDS; writes the scaled table.
-__global__ __launch_bounds__(256) void k_tab_laplace(int M, int nmodes, const GeomDesc *__restrict__ geoms,
-                                                    const double *__restrict__ start,
-                                                    double *__restrict__ tab)
+// Laplace recursion for one (geometry, mode); writes the scaled table.
+// The Laplace equation multiplied by r^2,
+//   r^2 g_rr + r g_r - n^2 g + r^2 g_xx = 0,
+// gives for the Taylor coefficients about r (rho = r' - r) a recursion of
+// five terms (the form divided by r needs all previous rows):
+//   r^2 (i+1)(i+2) g_(i+2) = -[ r (i+1)(2i+1) g_(i+1) + (i^2 - n^2) g_i
+//                               + r^2 h_i + 2 r h_(i-1) + h_(i-2) ],
+//   h_m = (k+1)(k+2) g_(m, k+2);  and the same in r1 for the source index.
+// One wave runs one recursion with lane k holding the x index k of the last
+// four rows; the k + 2 entries come from lane k + 2 by a shuffle.  Waves 0
+// and 1 run the r recursion of the columns b = 0 and 1 (rows staged in LDS),
+// then the four waves share the r1 recursions, one per a.
+constexpr int kLapThreads = 256;
+__device__ __forceinline__ double lap_step(double c1, double c0, double s2, double s1, double inv, double kk,
+                                           double g1, double g0, double h0, double hm1, double hm2)
 {
-    extern __shared__ double t[];      // (M+1)^3 compact entries
+    // -(c1 g_(i+1) + c0 g_i + kk (s2 h_i + s1 h_(i-1) + h_(i-2))) / (s2 (i+1)(i+2)), inv = -1/(...)
+    return (c1 * g1 + c0 * g0 + kk * (s2 * h0 + s1 * hm1 + hm2)) * inv;
+}
+
+__global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, const GeomDesc *__restrict__ geoms,
+                                                            const double *__restrict__ start,
+                                                            double *__restrict__ tab)
+{
+    __shared__ double col[2][AXF_MAX_ORDER + 1][2 * AXF_MAX_ORDER + 1];   // rows (a, b) for b = 0, 1
     __shared__ double fact[2 * AXF_MAX_ORDER + 2];
     const int K = 2 * M;
     const int g = blockIdx.x / nmodes, n = blockIdx.x - g * nmodes;
     const GeomDesc gd = geoms[g];
     const double r = gd.rout, r1 = gd.rin;
     const double n2 = (double)n * n;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, k = tid & 63;
+    const double kk = (k + 1.0) * (k + 2.0);
+    double *out = tab + ((size_t)g * nmodes + n) * (size_t)((M + 1) * (M + 1) * (M + 1));
     if (tid == 0) {
         double f = 1.0;
         for (int c = 0; c <= K; ++c) {
@@ -315,65 +336,50 @@ __global__ __launch_bounds__(256) void k_tab_laplace(int M, int nmodes, const Ge
         }
     }
     const double *st = start + ((size_t)g * nmodes + n) * 4 * (K + 1);
-    for (int e = tid; e < K + 1; e += blockDim.x) {
-        t[table_row(M, 0, 0) + e] = st[e];
-        if (M >= 1) {
-            if (e <= K - 1) {
-                t[table_row(M, 1, 0) + e] = st[(K + 1) + e];
-                t[table_row(M, 0, 1) + e] = st[2 * (K + 1) + e];
-            }
-            if (e <= K - 2) t[table_row(M, 1, 1) + e] = st[3 * (K + 1) + e];
+    // r recursion of column b (wave b): rows (i, b), i = 0..M, length K + 1 - i - b
+    if (w < 2 && (w == 0 || M >= 1)) {
+        const int bcol = w;
+        const int len0 = K + 1 - bcol;
+        double gm2 = 0.0, gm1 = 0.0;                           // rows i-2, i-1
+        double g0 = k < len0 ? st[(bcol == 0 ? 0 : 2) * (K + 1) + k] : 0.0;          // row 0
+        double g1 = (M >= 1 && k < len0 - 1) ? st[(bcol == 0 ? 1 : 3) * (K + 1) + k] : 0.0;   // row 1
+        if (k < len0) col[bcol][0][k] = g0;
+        if (M >= 1 && k < len0 - 1) col[bcol][1][k] = g1;
+        for (int i = 0; i + 2 <= M; ++i) {
+            const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
+            const double c1 = r * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
+            const double inv = -1.0 / (r * r * (i + 1.0) * (i + 2.0));
+            const double gn = lap_step(c1, c0, r * r, 2.0 * r, inv, kk, g1, g0, h0, i >= 1 ? hm1 : 0.0,
+                                       i >= 2 ? hm2 : 0.0);
+            gm2 = gm1;
+            gm1 = g0;
+            g0 = g1;
+            g1 = k <= K - (i + 2) - bcol ? gn : 0.0;
+            if (k <= K - (i + 2) - bcol) col[bcol][i + 2][k] = g1;
         }
     }
     __syncthreads();
-    // The Laplace equation multiplied by r^2,
-    //   r^2 g_rr + r g_r - n^2 g + r^2 g_xx = 0,
-    // gives for the Taylor coefficients about r (rho = r' - r) a recursion of
-    // five terms (the form divided by r needs all previous rows):
-    //   r^2 (i+1)(i+2) g_(i+2) = -[ r (i+1)(2i+1) g_(i+1) + (i^2 - n^2) g_i
-    //                               + r^2 h_i + 2 r h_(i-1) + h_(i-2) ],
-    //   h_m = (k+1)(k+2) g_(m, k+2);  and the same in r1 for the source index.
-    // r-recursion for b = 0, 1
-    for (int i = 0; i + 2 <= M; ++i) {
-        const int len0 = K - i - 2 + 1, len1 = K - i - 3 + 1;
-        const double c1 = r * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
-        const double inv = -1.0 / (r * r * (i + 1.0) * (i + 2.0));
-        for (int e = tid; e < len0 + len1; e += blockDim.x) {
-            const int j = e < len0 ? 0 : 1, k = e < len0 ? e : e - len0;
-            const double kk = (k + 1.0) * (k + 2.0);
-            double v = c1 * t[table_row(M, i + 1, j) + k] + c0 * t[table_row(M, i, j) + k] +
-                       r * r * kk * t[table_row(M, i, j) + k + 2];
-            if (i >= 1) v += 2.0 * r * kk * t[table_row(M, i - 1, j) + k + 2];
-            if (i >= 2) v += kk * t[table_row(M, i - 2, j) + k + 2];
-            t[table_row(M, i + 2, j) + k] = v * inv;
+    // r1 recursion for each a: rows (a, j), j = 0..M, length K + 1 - a - j
+    for (int a = w; a <= M; a += kLapThreads / 64) {
+        double gm2 = 0.0, gm1 = 0.0;
+        double g0 = k <= K - a ? col[0][a][k] : 0.0;
+        double g1 = (M >= 1 && k <= K - a - 1) ? col[1][a][k] : 0.0;
+        const double fk = k <= K ? fact[k] * gd.invh : 0.0;
+        if (k <= K - a) out[table_row(M, a, 0) + k] = g0 * fk;
+        if (M >= 1 && k <= K - a - 1) out[table_row(M, a, 1) + k] = g1 * fk;
+        for (int j = 0; j + 2 <= M; ++j) {
+            const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
+            const double c1 = r1 * (j + 1.0) * (2.0 * j + 1.0), c0 = (double)j * j - n2;
+            const double inv = -1.0 / (r1 * r1 * (j + 1.0) * (j + 2.0));
+            const double gn = lap_step(c1, c0, r1 * r1, 2.0 * r1, inv, kk, g1, g0, h0, j >= 1 ? hm1 : 0.0,
+                                       j >= 2 ? hm2 : 0.0);
+            gm2 = gm1;
+            gm1 = g0;
+            g0 = g1;
+            const bool valid = k <= K - a - (j + 2);
+            g1 = valid ? gn : 0.0;
+            if (valid) out[table_row(M, a, j + 2) + k] = g1 * fk;
         }
-        __syncthreads();
-    }
-    // r1-recursion for all a
-    for (int j = 0; j + 2 <= M; ++j) {
-        const double c1 = r1 * (j + 1.0) * (2.0 * j + 1.0), c0 = (double)j * j - n2;
-        const double inv = -1.0 / (r1 * r1 * (j + 1.0) * (j + 2.0));
-        const int L0 = K - j - 1;                   // k range of a = 0
-        for (int e = tid; e < (M + 1) * L0; e += blockDim.x) {
-            const int a = e / L0, k = e - a * L0;
-            if (k > K - a - j - 2) continue;
-            const double kk = (k + 1.0) * (k + 2.0);
-            double v = c1 * t[table_row(M, a, j + 1) + k] + c0 * t[table_row(M, a, j) + k] +
-                       r1 * r1 * kk * t[table_row(M, a, j) + k + 2];
-            if (j >= 1) v += 2.0 * r1 * kk * t[table_row(M, a, j - 1) + k + 2];
-            if (j >= 2) v += kk * t[table_row(M, a, j - 2) + k + 2];
-            t[table_row(M, a, j + 2) + k] = v * inv;
-        }
-        __syncthreads();
-    }
-    // scaled output: c! g / h
-    double *out = tab + ((size_t)g * nmodes + n) * (size_t)((M + 1) * (M + 1) * (M + 1));
-    const int nrow = (M + 1) * (M + 1);
-    const int wid = tid >> 6, lane = tid & 63;
-    for (int row = wid; row < nrow; row += blockDim.x >> 6) {
-        int a = row / (M + 1), b = row - a * (M + 1);
-        int base = table_row(M, a, b), len = K + 1 - a - b;
-        for (int c = lane; c < len; c += 64) out[base + c] = t[base + c] * fact[c] * gd.invh;
     }
 }
 
@@ -407,11 +413,8 @@ void build_tables(Plan &pl, hipStream_t st)
     double *dstart = reinterpret_cast<double *>(pl.tab_scratch) + 4 * (size_t)ng;
     AXF_HIP(hipMemcpyAsync(dgeo, geoms.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
     size_t sm_start = start_lds_bytes(M, nm);
-    size_t sm_lap = sizeof(double) * TS;
     static bool attr_done[64] = {};
     if (!attr_done[pl.device & 63]) {
-        AXF_HIP(hipFuncSetAttribute((const void *)k_tab_laplace, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    sizeof(double) * (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 1)));
         AXF_HIP(hipFuncSetAttribute((const void *)k_tab_start, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)start_lds_bytes(AXF_MAX_ORDER, AXF_MAX_MODES)));
         attr_done[pl.device & 63] = true;
@@ -419,7 +422,7 @@ void build_tables(Plan &pl, hipStream_t st)
     k_tab_start<<<ng, kStartThreads, sm_start, st>>>(M, nm, pl.chistar, dgeo, dstart);
     // tables of level l start at geometry index 12 * (2^l - 4)
     double *tab = pl.lev[2].tab;
-    k_tab_laplace<<<ng * nm, 256, sm_lap, st>>>(M, nm, dgeo, dstart, tab);
+    k_tab_laplace<<<ng * nm, kLapThreads, 0, st>>>(M, nm, dgeo, dstart, tab);
     AXF_HIP(hipGetLastError());
     // the host geometry list must outlive the copy
     AXF_HIP(hipStreamSynchronize(st));
