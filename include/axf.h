@@ -174,7 +174,7 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHAS
 
 /* Algorithmic work of one evaluation (host outputs, any may be NULL):
  * near-field ring pairs, S2L box pairs, and FP64 operation counts per phase
- * ([AXF_NUM_PHASES], fma = 2).  Pair sums: 21 flops per pair + 9 per AGM
+ * ([AXF_NUM_PHASES], fma = 2).  Pair sums: 24 flops per pair + 9 per AGM
  * iteration + 3 per recursion step + (N + 6) per pair on the backward branch
  * + 4 per mode and right-hand side, with the iteration and step counts each
  * pair needs taken from a census of the plan's pairs (sampled to about 3e7

@@ -421,7 +421,7 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
                 pair_census(pl, true, pl.census_direct, nullptr);
                 pl.census_done = true;
             }
-            // FP64 operation model (fma = 2).  A pair costs 21 flops of
+            // FP64 operation model (fma = 2).  A pair costs 24 flops of
             // geometry, start values and chi, 9 per AGM iteration, 3 per
             // recursion step, N + 6 more on the backward branch (asymptotic
             // start and normalisation) and 4 per mode and right-hand side of
@@ -431,7 +431,7 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
             const double M = pl.M;
             const double c3 = (M + 1) * (M + 2) * (M + 3) / 6.0;   // C(M+3, 3): one separable pass
             auto pair_flops = [&](const double *cs) {
-                return cs[0] * (21.0 + 4.0 * Nm * R) + 9.0 * cs[2] + 3.0 * cs[3] + cs[1] * (N + 6.0);
+                return cs[0] * (24.0 + 4.0 * Nm * R) + 9.0 * cs[2] + 3.0 * cs[3] + cs[1] * (N + 6.0);
             };
             double nbox_up = 0, nbox_down = 0;   // M2M parents, L2L children
             for (int l = 2; l < pl.d; ++l) nbox_up += pl.src.nocc[l];

@@ -99,13 +99,17 @@ __device__ __forceinline__ PairStart pair_start(double rm2, double rp2, double r
         double an = 0.5 * (a + b);
         b = fast_sqrt(a * b);
         a = an;
-        if (c <= 0x1p-30 * a) break;
+        if (c <= 0x1p-15 * a) break;
         c = 0.5 * (a - b);
         w *= 2.0;
         csum = fma(w * c, c, csum);
     }
+    // stopped at c <= 2^-15 a: the next half-difference c' = c^2 / (4 a) is
+    // below 2^-32 a and the limit is a - c' to 2^-64, so
+    // 1 / limit = (1/a)(1 + c^2 / (4 a^2)); the omitted csum term is ~2^-56.
     PairStart ps;
-    ps.g0 = 0.5 * fast_rcp(a);
+    const double ra = fast_rcp(a);
+    ps.g0 = 0.5 * ra * fma(0.25 * c * c, ra * ra, 1.0);
     ps.g1 = ps.g0 * csum * 0.5 * inv_rr;
     ps.chi = (rp2 + rm2) * 0.25 * inv_rr;
     ps.dchi = rm2 * 0.5 * inv_rr;

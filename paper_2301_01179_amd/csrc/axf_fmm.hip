@@ -676,7 +676,6 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
 #pragma unroll
         for (int n = 0; n < NMB; ++n) {
             accum_mode<NMB, MODE>(A, n, bv.get(n), gprev, Ss[n], pd);
-            if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
         return;
     }
@@ -695,7 +694,6 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
         }
         accum_mode<NMB, MODE>(A, n, g, gprev, Ss[n], pd);
         // bound the scheduling window: keeps only a few modes' loads in flight
-        if ((n & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         if (n + 1 < NMB) {
             double gn;
             if (n == 0) {
@@ -1179,7 +1177,7 @@ void launch_leaf_batch(const BatchQueues &bq, hipStream_t st)
 
 // ------------------------------------------------------------- census
 // Work census of the pair sums for the flop model: per pair, the AGM
-// iterations to convergence (the criterion of pair_start) and the recursion
+// iterations to convergence (the criterion of pair_start, c <= 2^-15 a) and the recursion
 // steps the pair itself needs (forward: N - 1; backward: N + 3 +
 // 12 / sqrt(2 (chi - 1)), the count the backward branch uses for its worst
 // lane).  Sums per block: [pairs, backward pairs, AGM iterations, steps].
@@ -1196,7 +1194,7 @@ __device__ __forceinline__ void census_pair(double r, double z, double r1, doubl
         b = sqrt(a * b);
         a = an;
         ++it;
-        if (c <= 0x1p-30 * a) break;
+        if (c <= 0x1p-15 * a) break;
         c = 0.5 * (a - b);
     }
     const double dchi = rm2 / (2.0 * rr);

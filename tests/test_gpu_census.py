@@ -2,7 +2,7 @@
 on the same tree: near-field pairs (sources in the 3 x 3 neighbour leaves of
 each field point's leaf, coincident points excluded), pairs on the backward
 branch (chi >= chi*, chi* = cosh(32 acosh(1.008) / N)), AGM iterations to
-the convergence criterion c <= 2^-30 a, and recursion steps per pair
+the convergence criterion c <= 2^-15 a, and recursion steps per pair
 (N - 1 forward; N + 3 + ceil(12 / sqrt(2 (chi - 1))) backward)."""
 import math
 
@@ -38,7 +38,7 @@ def _expected(rs, zs, rf, zf, depth, nmodes):
             b = np.where(done, b, np.sqrt(a * b))
             a = np.where(done, a, an)
             it += ~done
-            done |= c <= 2.0 ** -30 * a
+            done |= c <= 2.0 ** -15 * a
             c = np.where(done, c, 0.5 * (a - b))
             if done.all():
                 break
