@@ -610,11 +610,11 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
             // acosh(1 + d) <= sqrt(2 d) makes the count conservative).
             const double dmin = wave_min(back ? ps.dchi : 1e300);
             int extra = 3 + (int)ceil(12.0 * __builtin_amdgcn_rsq(2.0 * dmin));
-            // steps above the stored modes, a multiple of 8
+            // steps above the stored modes, a multiple of 16
             int nsteps = nmodes - 1 + extra - (NMB - 1);
-            nsteps = (nsteps + 7) & ~7;
-            if (nsteps < 8) nsteps = 8;
-            if (NMB - 1 + nsteps > kMillerMax) nsteps = (kMillerMax - NMB + 1) & ~7;
+            nsteps = (nsteps + 15) & ~15;
+            if (nsteps < 16) nsteps = 16;
+            if (NMB - 1 + nsteps > kMillerMax) nsteps = (kMillerMax - NMB + 1) & ~15;
             const int ntop = __builtin_amdgcn_readfirstlane(NMB - 1 + nsteps);
             // lanes on the forward branch run the same steps on a harmless chi
             const double dch = back ? ps.dchi : dmin;
@@ -626,9 +626,9 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
                              fma(q, fast_rcp(4.0 * (1.0 - q) * nt * (nt + 1.0)), 1.0);
             double zc = 1.0;                                  // z_ntop
             double zp = t * fast_rcp(c_down.rho[ntop + 1]);   // z_(ntop+1)
-            for (int n = ntop; n >= NMB; n -= 8) {
+            for (int n = ntop; n >= NMB; n -= 16) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const double zm = fma(c_down.alpha[n - u] * chi, zc, -zp);
                     zp = zc;
                     zc = zm;
