@@ -240,39 +240,35 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
         if (active && j == 0) g00[n * L + k + 1] = (s * (n - 0.5)) / dd_d(k + 1.0);
         __syncthreads();
     }
-    // r-derivative and its r <-> r1 image: g10 goes out, g01 stays for g11
+    // r-derivative and its r <-> r1 image: g10 goes out, g01 stays for g11.
+    // Every (mode, k) entry is an independent sum: one thread each.
     if (M >= 1) {
-        for (int k = 0; k <= K - 1; ++k) {
+        for (int e = tid; e < (Nw + 1) * K; e += blockDim.x) {
+            const int m = e / K, k = e - m * K;
+            const int mm = m == 0 ? 1 : m - 1;
             dd s1 = dd_d(0.0), s2 = dd_d(0.0);
-            if (active)
-                for (int q = j; q <= k; q += lpm) {
-                    dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
-                    dd sp = a + b, sm = a - b;
-                    s1 = s1 + sp * pp[q] + sm * pm[q];
-                    s2 = s2 + sp * qp[q] + sm * qm[q];
-                }
-            s1 = lane_reduce(s1, lpm);
-            s2 = lane_reduce(s2, lpm);
-            if (active && j == 0) {
-                dd g = g00[n * L + k];
-                dd v10 = (s1 * (n - 0.5) - g) / dd_d(2.0 * r);
-                dd v01 = (s2 * (n - 0.5) - g) / dd_d(2.0 * r1);
-                g01[n * L + k] = v01;
-                if (n < nmodes) o[((size_t)n * 4 + 1) * L + k] = v10.hi;
+            for (int q = 0; q <= k; ++q) {
+                const dd a = g00[m * L + k - q], b = g00[mm * L + k - q];
+                const dd sp = a + b, sm = a - b;
+                s1 = s1 + sp * pp[q] + sm * pm[q];
+                s2 = s2 + sp * qp[q] + sm * qm[q];
             }
+            const dd g = g00[m * L + k];
+            g01[m * L + k] = (s2 * (m - 0.5) - g) / dd_d(2.0 * r1);
+            if (m < nmodes) o[((size_t)m * 4 + 1) * L + k] = ((s1 * (m - 0.5) - g) / dd_d(2.0 * r)).hi;
         }
         __syncthreads();
-        for (int k = 0; k <= K - 2; ++k) {
+        for (int e = tid; e < (Nw + 1) * (K - 1); e += blockDim.x) {
+            const int m = e / (K - 1), k = e - m * (K - 1);
+            if (m >= nmodes) continue;
+            const int mm = m == 0 ? 1 : m - 1;
             dd s = dd_d(0.0);
-            if (active)
-                for (int q = j; q <= k; q += lpm) {
-                    dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
-                    dd e = g01[n * L + k - q], f = g01[nm * L + k - q];
-                    s = s + (a + b) * dp[q] + (e + f) * pp[q] + (a - b) * dm[q] + (e - f) * pm[q];
-                }
-            s = lane_reduce(s, lpm);
-            if (active && j == 0 && n < nmodes)
-                o[((size_t)n * 4 + 3) * L + k] = ((s * (n - 0.5) - g01[n * L + k]) / dd_d(2.0 * r)).hi;
+            for (int q = 0; q <= k; ++q) {
+                const dd a = g00[m * L + k - q], b = g00[mm * L + k - q];
+                const dd e1 = g01[m * L + k - q], f1 = g01[mm * L + k - q];
+                s = s + (a + b) * dp[q] + (e1 + f1) * pp[q] + (a - b) * dm[q] + (e1 - f1) * pm[q];
+            }
+            o[((size_t)m * 4 + 3) * L + k] = ((s * (m - 0.5) - g01[m * L + k]) / dd_d(2.0 * r)).hi;
         }
     }
     // g00, g01 and the zero tails
