@@ -69,11 +69,12 @@ def copy_probe(torch, mib):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
 
 
-def read_traffic(kernel_file):
+def read_traffic(phase, kernel_file="axf_fmm.hip"):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary profiles/<phase>_traffic.txt, if it was taken on the current
+    kernel source (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "leaf_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{phase}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -292,11 +293,11 @@ def main():
 
     # roofline of the dominant kernel (evaluation passes)
     flops = work["flops"]
-    phases = ["p2m", "m2m", "s2l", "leaf"]
+    phases = ["p2m", "m2m", "l2l", "s2l", "leaf"]
     dom = max(phases, key=lambda p: timing[p][0])
     ms_dom, launches = timing[dom]
     achieved = flops[dom] / (ms_dom / 1e3 / args.steps) / 1e12 if ms_dom > 0 else 0.0
-    traffic = read_traffic("axf_fmm.hip") if dom == "leaf" else None
+    traffic = read_traffic(dom)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
                 "traffic": traffic, "kernel": dom,

@@ -163,10 +163,11 @@ enum {
     AXF_PHASE_GATHER = 0,  /* strengths into tree order                      */
     AXF_PHASE_P2M = 1,     /* leaf moments, eq. analysis:moments             */
     AXF_PHASE_M2M = 2,     /* upward pass, eq. analysis:shift                */
-    AXF_PHASE_S2L = 3,     /* downward pass: S2L + local shift               */
+    AXF_PHASE_S2L = 3,     /* downward pass: S2L translations                */
     AXF_PHASE_LEAF = 4,    /* local expansion + near field at the leaves     */
     AXF_PHASE_DIRECT = 5,  /* direct modal sum                               */
-    AXF_NUM_PHASES = 6
+    AXF_PHASE_L2L = 6,     /* downward pass: local shifts, eq. analysis:l2l  */
+    AXF_NUM_PHASES = 7
 };
 axf_status axf_plan_set_timing(axf_plan *plan, int32_t enable);
 axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHASES] */,
@@ -180,7 +181,7 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHAS
  * pair needs taken from a census of the plan's pairs (sampled to about 3e7
  * pairs for the direct sum); P2M 4 P C + 2 P per source; separable M2M
  * 24 C(M+3, 3) per parent box and channel, L2L 8 C(M+3, 3) per box and
- * channel; S2L 4 P^2 per box pair and channel; local
+ * channel (AXF_PHASE_L2L); S2L 4 P^2 per box pair and channel; local
  * evaluation 4 P C + 2 P per field point.  The census runs once, on the
  * first call that asks for flops, and synchronises the device. */
 axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs,

@@ -28,7 +28,7 @@ EXPORTED = [
     "axf_plan_census",
 ]
 
-PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct"]
+PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l"]
 
 
 class AxfError(RuntimeError):

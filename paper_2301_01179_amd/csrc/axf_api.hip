@@ -440,7 +440,8 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
             flops[AXF_PHASE_P2M] = (double)pl.src.n * (4.0 * P * C + 2.0 * P);
             // separable shifts: M2M 4 children in z + 2 parities in r, L2L r then z
             flops[AXF_PHASE_M2M] = nbox_up * C * c3 * 24.0;
-            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0 + nbox_down * C * c3 * 8.0;
+            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0;
+            flops[AXF_PHASE_L2L] = nbox_down * C * c3 * 8.0;
             flops[AXF_PHASE_LEAF] = pair_flops(pl.census_near) + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
             flops[AXF_PHASE_DIRECT] = pair_flops(pl.census_direct);
         }

@@ -1013,13 +1013,17 @@ void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t
 
 void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
-    // locals of the level's target boxes: shifted parent expansion, or zero
-    k_l2l<<<tgt.nocc[l] * pl.C, 256, 0, st>>>(pl.M, pl.C, l, tgt.box[l], l > 2 ? tgt.slot[l - 1] : nullptr,
-                                               l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
+    {
+        // locals of the level's target boxes: shifted parent expansion, or zero
+        PhaseTimer tm(pl, st, AXF_PHASE_L2L);
+        k_l2l<<<tgt.nocc[l] * pl.C, 256, 0, st>>>(pl.M, pl.C, l, tgt.box[l], l > 2 ? tgt.slot[l - 1] : nullptr,
+                                                   l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
+    }
+    PhaseTimer tm(pl, st, AXF_PHASE_S2L);
     switch (s2l_lb(pl.M)) {
-    case 1: launch_s2l_t<1, 8>(pl, src, tgt, l, st); break;
-    case 2: launch_s2l_t<2, 8>(pl, src, tgt, l, st); break;
-    default: launch_s2l_t<3, 8>(pl, src, tgt, l, st); break;
+    case 1: launch_s2l_t<1, 4>(pl, src, tgt, l, st); break;
+    case 2: launch_s2l_t<2, 4>(pl, src, tgt, l, st); break;
+    default: launch_s2l_t<3, 4>(pl, src, tgt, l, st); break;
     }
 }
 
@@ -1284,7 +1288,6 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
                                                    pl.lev[l].mom);
     }
     {
-        PhaseTimer tm_s2l(pl, st, AXF_PHASE_S2L);
         for (int l = 2; l <= d; ++l) {
             if (tgt.ntiles[l] == 0) continue;
             launch_s2l(pl, src, tgt, l, st);
@@ -1337,9 +1340,9 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
         if (!bq.ns2l[l]) continue;
         switch (s2l_lb(bq.M)) {
-        case 1: launch_s2l_batch<1, 8>(bq, l, st); break;
-        case 2: launch_s2l_batch<2, 8>(bq, l, st); break;
-        default: launch_s2l_batch<3, 8>(bq, l, st); break;
+        case 1: launch_s2l_batch<1, 4>(bq, l, st); break;
+        case 2: launch_s2l_batch<2, 4>(bq, l, st); break;
+        default: launch_s2l_batch<3, 4>(bq, l, st); break;
         }
     }
     if (bq.nleaf) {

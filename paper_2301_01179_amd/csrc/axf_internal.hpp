@@ -101,7 +101,7 @@ struct Side {
 // Shape of the tiled S2L: output slots of one (box, channel) are rows k
 // split into blocks of LB columns; LB is the smallest width whose slots fit
 // in four waves, the block has one wave per 64 slots, and a tile holds TB
-// target boxes.
+// target boxes (4: measured best against 2, 8 and 16 at M = 24).
 inline int s2l_slots(int M, int lb)
 {
     int s = 0;
@@ -115,7 +115,7 @@ inline int s2l_lb(int M)
     return 3;
 }
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
-inline int s2l_tb(int) { return 8; }
+inline int s2l_tb(int) { return 4; }
 // Offset groups of a level: the 27 interaction-list offsets of a (tile,
 // channel) are split over G blocks so that a level launches ~2048 waves.
 inline int s2l_group_count(int ntiles, int C, int M)
