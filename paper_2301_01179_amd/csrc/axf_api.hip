@@ -173,7 +173,7 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
     size_t ngeom = 12 * (((size_t)1 << (d + 1)) - 4);
-    sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS);
+    sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
     sz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     // offset groups of the S2L pass and their partial-sum buffer (one level
     // at a time, either side as targets)
@@ -193,7 +193,7 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].mom = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
         pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
-    double *tab = pl.expn.take<double>(ngeom * (size_t)pl.nmodes * pl.TS);
+    double *tab = pl.expn.take<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
     for (int l = 2; l <= d; ++l)
         pl.lev[l].tab = tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
     pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));

@@ -314,7 +314,24 @@ __global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int3
 // moments broadcast from LDS.  The forward sign (-1)^(j+l) is split into
 // (-1)^j on the staged moments and (-1)^l on the accumulators.  The result,
 // times (-1)^l / l!, is added to the locals that the L2L pass initialised.
-template <int LB, int TB>
+// Compiled S2L shapes: (LB, MW) with MW = M rounded up to a multiple of 4,
+// the window bound that the kernel reads in full; LB from the slot rule.
+#define AXF_S2L_SHAPES(Mv, F)                                            \
+    do {                                                                 \
+        const int mw_ = s2l_window(Mv);                                  \
+        if (s2l_lb(Mv) == 1) {                                           \
+            if (mw_ == 4) F(1, 4);                                       \
+            else if (mw_ == 8) F(1, 8);                                  \
+            else if (mw_ == 12) F(1, 12);                                \
+            else if (mw_ == 16) F(1, 16);                                \
+            else if (mw_ == 20) F(1, 20);                                \
+            else F(1, 24);                                               \
+        } else {                                                         \
+            F(2, 24);                                                    \
+        }                                                                \
+    } while (0)
+
+template <int LB, int TB, int MW>
 __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int level, int TS,
                                                  const int4 *__restrict__ tiles,      // station, parity, first, count
                                                  const int32_t *__restrict__ tslots,  // target slots of the tiles
@@ -325,7 +342,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                                                  double2 *__restrict__ loc, int item, int G,
                                                  double2 *__restrict__ part, int nocc)
 {
-    extern __shared__ double2 ms[];          // [TB][P] staged moments
+    extern __shared__ double2 ms[];          // [P][TB] staged moments, boxes interleaved
     __shared__ double invfact[AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
@@ -404,7 +421,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                     }
                     if (q & 1) v = make_double2(-v.x, -v.y);
                 }
-                ms[e] = v;
+                ms[p * TB + b] = v;
             }
             __syncthreads();
             if (fwd) {
@@ -415,23 +432,27 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                         for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
             }
             if (live) {
-                int pbase = 0;
+                // Row (k, i) of an outward table or (i, k) of an inward one,
+                // from the lane's first column l0: advanced by one row per i.
+                // The window is read whole (MW + LB entries, M <= MW): entries
+                // past c = 2M - k - i + LB - 1 only meet j > M - i, which is
+                // skipped, and the table allocation is padded past its last
+                // row.
+                const double *row = T + (outward ? table_row(M, k, 0) : table_row(M, 0, k)) + l0;
+                const int K2 = 2 * M + 1, inward0 = (M + 1) * K2 - (M * (M + 1)) / 2 - k;
+                const double2 *mrow = ms;
                 for (int i = 0; i <= M; ++i) {
-                    const int a_ = outward ? k : i, b_ = outward ? i : k;
-                    const double *row = T + table_row(M, a_, b_);
-                    const int rl = 2 * M - a_ - b_;     // last valid c
                     const int jn = M - i;
-                    // the lane's whole window for this i: all loads in flight at once
-                    constexpr int NW = AXF_MAX_ORDER + LB;
+                    constexpr int NW = MW + LB;
                     double w[NW];
 #pragma unroll
-                    for (int q = 0; q < NW; ++q) w[q] = (q < jn + LB) ? row[min(l0 + q, rl)] : 0.0;
+                    for (int q = 0; q < NW; ++q) w[q] = row[q];
 #pragma unroll
-                    for (int j = 0; j <= AXF_MAX_ORDER; ++j) {
+                    for (int j = 0; j <= MW; ++j) {
                         if (j <= jn) {
 #pragma unroll
                             for (int b = 0; b < TB; ++b) {
-                                const double2 sv = ms[b * P + pbase + j];
+                                const double2 sv = mrow[j * TB + b];
 #pragma unroll
                                 for (int u = 0; u < LB; ++u) {
                                     acc[u][b].x = fma(w[j + u], sv.x, acc[u][b].x);
@@ -440,7 +461,8 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                             }
                         }
                     }
-                    pbase += jn + 1;
+                    mrow += (jn + 1) * TB;
+                    row += outward ? K2 - k - i : inward0 - (M + 1) * i;
                 }
             }
             if (fwd) {
@@ -492,7 +514,7 @@ __global__ __launch_bounds__(256) void k_s2l_reduce(int64_t n, int G, const doub
     loc[e] = v;
 }
 
-template <int LB, int TB>
+template <int LB, int TB, int MW>
 __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
                                                   const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
                                                   const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
@@ -500,7 +522,7 @@ __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, i
                                                   double2 *__restrict__ loc, int G, double2 *__restrict__ part,
                                                   int nocc)
 {
-    s2l_tile_body<LB, TB>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
+    s2l_tile_body<LB, TB, MW>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
                           part, nocc);
 }
 
@@ -996,13 +1018,13 @@ SideView view_of(const Side &s)
     return v;
 }
 
-template <int LB, int TB>
+template <int LB, int TB, int MW>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     size_t shm = sizeof(double2) * (size_t)TB * pl.P;
     const int G = tgt.s2l_groups[l];
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
-    k_s2l_tile<LB, TB><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
+    k_s2l_tile<LB, TB, MW><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
         pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],
         pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l]);
     if (G > 1) {
@@ -1020,11 +1042,9 @@ void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t s
                                                    l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
     }
     PhaseTimer tm(pl, st, AXF_PHASE_S2L);
-    switch (s2l_lb(pl.M)) {
-    case 1: launch_s2l_t<1, 4>(pl, src, tgt, l, st); break;
-    case 2: launch_s2l_t<2, 4>(pl, src, tgt, l, st); break;
-    default: launch_s2l_t<3, 4>(pl, src, tgt, l, st); break;
-    }
+#define AXF_S2L_LAUNCH(LB, MW) launch_s2l_t<LB, 4, MW>(pl, src, tgt, l, st)
+    AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH);
+#undef AXF_S2L_LAUNCH
 }
 
 template <int NMB, int MODE>
@@ -1115,7 +1135,7 @@ __global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, con
     }
 }
 
-template <int LB, int TB>
+template <int LB, int TB, int MW>
 __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
                                              int nmodes, int TS, int l)
 {
@@ -1123,7 +1143,7 @@ __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, con
         const int2 it = q[i];
         const ProbDev &pd = P[it.x];
         __syncthreads();
-        s2l_tile_body<LB, TB>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
+        s2l_tile_body<LB, TB, MW>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
                               pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0);
     }
 }
@@ -1155,13 +1175,13 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
     }
 }
 
-template <int LB, int TB>
+template <int LB, int TB, int MW>
 void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
 {
     const int P = (bq.M + 1) * (bq.M + 2) / 2;
     size_t shm = sizeof(double2) * (size_t)TB * P;
     int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
-    kb_s2l<LB, TB><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
+    kb_s2l<LB, TB, MW><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }
 
 template <int NMB>
@@ -1339,11 +1359,9 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
         if (bq.nl2l[l])
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
         if (!bq.ns2l[l]) continue;
-        switch (s2l_lb(bq.M)) {
-        case 1: launch_s2l_batch<1, 4>(bq, l, st); break;
-        case 2: launch_s2l_batch<2, 4>(bq, l, st); break;
-        default: launch_s2l_batch<3, 4>(bq, l, st); break;
-        }
+#define AXF_S2L_LAUNCH(LB, MW) launch_s2l_batch<LB, 4, MW>(bq, l, st)
+        AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH);
+#undef AXF_S2L_LAUNCH
     }
     if (bq.nleaf) {
 #define AXF_LEAFB(B)                          \

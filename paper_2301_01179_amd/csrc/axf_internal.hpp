@@ -108,14 +108,14 @@ inline int s2l_slots(int M, int lb)
     for (int k = 0; k <= M; ++k) s += (M + 1 - k + lb - 1) / lb;
     return s;
 }
-inline int s2l_lb(int M)
-{
-    for (int lb = 1; lb <= 3; ++lb)
-        if (s2l_slots(M, lb) <= 256) return lb;
-    return 3;
-}
+inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
 inline int s2l_tb(int) { return 4; }
+// Window bound of the S2L lanes: M rounded up to a multiple of 4.
+inline int s2l_window(int M) { return M <= 4 ? 4 : (M + 3) / 4 * 4; }
+// Doubles past the last table: a lane reads its whole window, up to
+// s2l_window + s2l_lb - 1 entries past the start of the table's last row.
+constexpr size_t kTablePad = 64;
 // Offset groups of a level: the 27 interaction-list offsets of a (tile,
 // channel) are split over G blocks so that a level launches ~2048 waves.
 inline int s2l_group_count(int ntiles, int C, int M)
