@@ -302,6 +302,59 @@ __global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int3
 }
 
 // ------------------------------------------------------- S2L, tiled form
+// One offset's contraction for one lane: rows i = 0..M of the staged
+// moments against the table row (k, i) of an outward offset or (i, k) of an
+// inward one, from the lane's first column l0 (one row advance per i).  With
+// FIX the order is the compile-time MW and every loop is unrolled: each row
+// loads exactly its window (M - i + LB entries) with no branches.  Otherwise
+// the window is read whole (MW + LB entries, M <= MW): entries past c = 2M -
+// k - i + LB - 1 only meet j > M - i, which is skipped, and the table
+// allocation is padded past its last row.
+template <int LB, int TB, int MW, bool FIX>
+__device__ __forceinline__ void s2l_row(int M, int i, const double *&row, const double2 *&mrow, int k, bool outward,
+                                        double2 (&acc)[LB][TB])
+{
+    constexpr int NW = MW + LB;
+    const int jn = M - i;
+    double w[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q)
+        if (!FIX || q < jn + LB) w[q] = row[q];
+#pragma unroll
+    for (int j = 0; j <= MW; ++j) {
+        if (j <= jn) {
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                const double2 sv = mrow[j * TB + b];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    acc[u][b].x = fma(w[j + u], sv.x, acc[u][b].x);
+                    acc[u][b].y = fma(w[j + u], sv.y, acc[u][b].y);
+                }
+            }
+        }
+    }
+    mrow += (jn + 1) * TB;
+    // next row: (k, i + 1) is 2M + 1 - k - i entries on, (i + 1, k) one
+    // a-slab of the table less the rows b < k of slab i and b >= k of slab i + 1
+    row += outward ? 2 * M + 1 - k - i : (M + 1) * (2 * M + 1) - (M * (M + 1)) / 2 - k - (M + 1) * i;
+}
+
+template <int LB, int TB, int MW, bool FIX>
+__device__ __forceinline__ void s2l_rows(int M, const double *__restrict__ T, int k, int l0, bool outward,
+                                         const double2 *ms, double2 (&acc)[LB][TB])
+{
+    const double *row = T + (outward ? table_row(M, k, 0) : table_row(M, 0, k)) + l0;
+    const double2 *mrow = ms;
+    if constexpr (FIX) {
+#pragma unroll
+        for (int i = 0; i <= MW; ++i) s2l_row<LB, TB, MW, true>(MW, i, row, mrow, k, outward, acc);
+    } else {
+#pragma unroll 1
+        for (int i = 0; i <= M; ++i) s2l_row<LB, TB, MW, false>(M, i, row, mrow, k, outward, acc);
+    }
+}
+
 // One block of W waves per (tile, channel).  A tile is up to TB occupied
 // target boxes of one radial station with the same z parity, so that every
 // box of the tile has the same interaction-list offsets (dr, dz) and
@@ -314,24 +367,32 @@ __global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int3
 // moments broadcast from LDS.  The forward sign (-1)^(j+l) is split into
 // (-1)^j on the staged moments and (-1)^l on the accumulators.  The result,
 // times (-1)^l / l!, is added to the locals that the L2L pass initialised.
-// Compiled S2L shapes: (LB, MW) with MW = M rounded up to a multiple of 4,
-// the window bound that the kernel reads in full; LB from the slot rule.
+// Compiled S2L shapes: (LB, MW, FIX) with MW = M rounded up to a multiple
+// of 4, the window bound, LB from the slot rule, and FIX = (M == MW): the
+// fully unrolled rows of a compile-time order.
 #define AXF_S2L_SHAPES(Mv, F)                                            \
     do {                                                                 \
         const int mw_ = s2l_window(Mv);                                  \
-        if (s2l_lb(Mv) == 1) {                                           \
-            if (mw_ == 4) F(1, 4);                                       \
-            else if (mw_ == 8) F(1, 8);                                  \
-            else if (mw_ == 12) F(1, 12);                                \
-            else if (mw_ == 16) F(1, 16);                                \
-            else if (mw_ == 20) F(1, 20);                                \
-            else F(1, 24);                                               \
+        if (s2l_lb(Mv) == 2) {                                           \
+            if ((Mv) == 24) F(2, 24, true);                              \
+            else F(2, 24, false);                                        \
+        } else if ((Mv) == mw_) {                                        \
+            if (mw_ == 4) F(1, 4, true);                                 \
+            else if (mw_ == 8) F(1, 8, true);                            \
+            else if (mw_ == 12) F(1, 12, true);                          \
+            else if (mw_ == 16) F(1, 16, true);                          \
+            else F(1, 20, true);                                         \
         } else {                                                         \
-            F(2, 24);                                                    \
+            if (mw_ == 4) F(1, 4, false);                                \
+            else if (mw_ == 8) F(1, 8, false);                           \
+            else if (mw_ == 12) F(1, 12, false);                         \
+            else if (mw_ == 16) F(1, 16, false);                         \
+            else if (mw_ == 20) F(1, 20, false);                         \
+            else F(1, 24, false);                                        \
         }                                                                \
     } while (0)
 
-template <int LB, int TB, int MW>
+template <int LB, int TB, int MW, bool FIX>
 __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int level, int TS,
                                                  const int4 *__restrict__ tiles,      // station, parity, first, count
                                                  const int32_t *__restrict__ tslots,  // target slots of the tiles
@@ -432,38 +493,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                         for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
             }
             if (live) {
-                // Row (k, i) of an outward table or (i, k) of an inward one,
-                // from the lane's first column l0: advanced by one row per i.
-                // The window is read whole (MW + LB entries, M <= MW): entries
-                // past c = 2M - k - i + LB - 1 only meet j > M - i, which is
-                // skipped, and the table allocation is padded past its last
-                // row.
-                const double *row = T + (outward ? table_row(M, k, 0) : table_row(M, 0, k)) + l0;
-                const int K2 = 2 * M + 1, inward0 = (M + 1) * K2 - (M * (M + 1)) / 2 - k;
-                const double2 *mrow = ms;
-                for (int i = 0; i <= M; ++i) {
-                    const int jn = M - i;
-                    constexpr int NW = MW + LB;
-                    double w[NW];
-#pragma unroll
-                    for (int q = 0; q < NW; ++q) w[q] = row[q];
-#pragma unroll
-                    for (int j = 0; j <= MW; ++j) {
-                        if (j <= jn) {
-#pragma unroll
-                            for (int b = 0; b < TB; ++b) {
-                                const double2 sv = mrow[j * TB + b];
-#pragma unroll
-                                for (int u = 0; u < LB; ++u) {
-                                    acc[u][b].x = fma(w[j + u], sv.x, acc[u][b].x);
-                                    acc[u][b].y = fma(w[j + u], sv.y, acc[u][b].y);
-                                }
-                            }
-                        }
-                    }
-                    mrow += (jn + 1) * TB;
-                    row += outward ? K2 - k - i : inward0 - (M + 1) * i;
-                }
+                s2l_rows<LB, TB, MW, FIX>(FIX ? MW : M, T, k, l0, outward, ms, acc);
             }
             if (fwd) {
 #pragma unroll
@@ -514,7 +544,7 @@ __global__ __launch_bounds__(256) void k_s2l_reduce(int64_t n, int G, const doub
     loc[e] = v;
 }
 
-template <int LB, int TB, int MW>
+template <int LB, int TB, int MW, bool FIX>
 __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, int level, int TS,
                                                   const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
                                                   const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
@@ -522,7 +552,7 @@ __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, i
                                                   double2 *__restrict__ loc, int G, double2 *__restrict__ part,
                                                   int nocc)
 {
-    s2l_tile_body<LB, TB, MW>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
+    s2l_tile_body<LB, TB, MW, FIX>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
                           part, nocc);
 }
 
@@ -1018,13 +1048,13 @@ SideView view_of(const Side &s)
     return v;
 }
 
-template <int LB, int TB, int MW>
+template <int LB, int TB, int MW, bool FIX>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     size_t shm = sizeof(double2) * (size_t)TB * pl.P;
     const int G = tgt.s2l_groups[l];
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
-    k_s2l_tile<LB, TB, MW><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
+    k_s2l_tile<LB, TB, MW, FIX><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
         pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],
         pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l]);
     if (G > 1) {
@@ -1042,7 +1072,7 @@ void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t s
                                                    l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
     }
     PhaseTimer tm(pl, st, AXF_PHASE_S2L);
-#define AXF_S2L_LAUNCH(LB, MW) launch_s2l_t<LB, 4, MW>(pl, src, tgt, l, st)
+#define AXF_S2L_LAUNCH(LB, MW, FIX) launch_s2l_t<LB, 4, MW, FIX>(pl, src, tgt, l, st)
     AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH);
 #undef AXF_S2L_LAUNCH
 }
@@ -1135,7 +1165,7 @@ __global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, con
     }
 }
 
-template <int LB, int TB, int MW>
+template <int LB, int TB, int MW, bool FIX>
 __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n, int M,
                                              int nmodes, int TS, int l)
 {
@@ -1143,7 +1173,7 @@ __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, con
         const int2 it = q[i];
         const ProbDev &pd = P[it.x];
         __syncthreads();
-        s2l_tile_body<LB, TB, MW>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
+        s2l_tile_body<LB, TB, MW, FIX>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
                               pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0);
     }
 }
@@ -1175,13 +1205,13 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
     }
 }
 
-template <int LB, int TB, int MW>
+template <int LB, int TB, int MW, bool FIX>
 void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
 {
     const int P = (bq.M + 1) * (bq.M + 2) / 2;
     size_t shm = sizeof(double2) * (size_t)TB * P;
     int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
-    kb_s2l<LB, TB, MW><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
+    kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }
 
 template <int NMB>
@@ -1359,7 +1389,7 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
         if (bq.nl2l[l])
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
         if (!bq.ns2l[l]) continue;
-#define AXF_S2L_LAUNCH(LB, MW) launch_s2l_batch<LB, 4, MW>(bq, l, st)
+#define AXF_S2L_LAUNCH(LB, MW, FIX) launch_s2l_batch<LB, 4, MW, FIX>(bq, l, st)
         AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH);
 #undef AXF_S2L_LAUNCH
     }
