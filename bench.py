@@ -343,7 +343,7 @@ def main():
         "ms_gpu_direct": t_direct * 1e3,
         "fmm_vs_direct_speedup": t_direct / t_step,
         "fmm_vs_direct_speedup_eval_only": t_direct / t_eval,
-        "near_pairs": work["near_pairs"], "s2l_box_pairs": work["s2l_pairs"],
+        "near_pairs": work["near_pairs"], "s2l_box_pairs": work["s2l_pairs"], "s2l_units": work["s2l_units"],
         "near_census": {"backward_fraction": census["backward"] / max(census["pairs"], 1.0),
                         "agm_iterations_per_pair": census["agm_iterations"] / max(census["pairs"], 1.0),
                         "recursion_steps_per_pair": census["steps"] / max(census["pairs"], 1.0),

@@ -174,17 +174,20 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHAS
                                 int32_t *launches /* host [AXF_NUM_PHASES] */);
 
 /* Algorithmic work of one evaluation (host outputs, any may be NULL):
- * near-field ring pairs, S2L box pairs, and FP64 operation counts per phase
- * ([AXF_NUM_PHASES], fma = 2).  Pair sums: 24 flops per pair + 9 per AGM
- * iteration + 3 per recursion step + (N + 6) per pair on the backward branch
- * + 4 per mode and right-hand side, with the iteration and step counts each
- * pair needs taken from a census of the plan's pairs (sampled to about 3e7
- * pairs for the direct sum); P2M 4 P C + 2 P per source; separable M2M
- * 24 C(M+3, 3) per parent box and channel, L2L 8 C(M+3, 3) per box and
- * channel (AXF_PHASE_L2L); S2L 4 P^2 per box pair and channel; local
- * evaluation 4 P C + 2 P per field point.  The census runs once, on the
- * first call that asks for flops, and synchronises the device. */
-axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs,
+ * near-field ring pairs, S2L box pairs, S2L units and FP64 operation counts
+ * per phase ([AXF_NUM_PHASES], fma = 2).  An S2L unit is a target box with
+ * the source boxes at offsets (dr, dz) and (dr, -dz) of its interaction list
+ * (section 2.2), either of them occupied: the two share one table (the
+ * derivatives' x-parity) and one P x P contraction.  Pair sums: 24 flops per
+ * pair + 9 per AGM iteration + 3 per recursion step + (N + 6) per pair on
+ * the backward branch + 4 per mode and right-hand side, with the iteration
+ * and step counts each pair needs taken from a census of the plan's pairs
+ * (sampled to about 3e7 pairs for the direct sum); P2M 4 P C + 2 P per
+ * source; separable M2M 24 C(M+3, 3) per parent box and channel, L2L
+ * 8 C(M+3, 3) per box and channel (AXF_PHASE_L2L); S2L 4 P^2 per unit and
+ * channel; local evaluation 4 P C + 2 P per field point.  The census runs
+ * once, on the first call that asks for flops, and synchronises the device. */
+axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs, int64_t *s2l_units,
                          double *flops /* host [AXF_NUM_PHASES] */);
 
 /* The pair census behind the flop model (host outputs, either may be NULL):

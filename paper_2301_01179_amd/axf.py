@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.axf_last_error.restype = ctypes.c_char_p
     lib.axf_plan_set_timing.argtypes = [vp, i32]
     lib.axf_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i32)]
-    lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(ctypes.c_double)]
+    lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(i64), P(ctypes.c_double)]
     lib.axf_plan_table.argtypes = [vp, i32, i32, i32, i32, P(ctypes.c_double)]
     lib.axf_plan_census.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double)]
     for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
@@ -186,11 +186,13 @@ class Plan:
         return {p: (ms[i], n[i]) for i, p in enumerate(PHASES)}
 
     def work(self) -> dict:
-        """Near pairs, S2L box pairs and the per-phase FP64 flop model."""
-        near, s2l = ctypes.c_int64(), ctypes.c_int64()
+        """Near pairs, S2L box pairs, S2L units (target box with the offset
+        pair (dr, +-dz)) and the per-phase FP64 flop model."""
+        near, s2l, units = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         fl = (ctypes.c_double * len(PHASES))()
-        _check(_lib.axf_plan_work(self._h, ctypes.byref(near), ctypes.byref(s2l), fl), "axf_plan_work")
-        return {"near_pairs": near.value, "s2l_pairs": s2l.value,
+        _check(_lib.axf_plan_work(self._h, ctypes.byref(near), ctypes.byref(s2l), ctypes.byref(units), fl),
+               "axf_plan_work")
+        return {"near_pairs": near.value, "s2l_pairs": s2l.value, "s2l_units": units.value,
                 "flops": {p: fl[i] for i, p in enumerate(PHASES)}}
 
     def census(self) -> dict:

@@ -407,13 +407,15 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms, int32_t *launches)
     })
 }
 
-axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs, double *flops)
+axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs, int64_t *s2l_units,
+                         double *flops)
 {
     AXF_TRY({
         AXF_REQUIRE(plan, AXF_ERR_INVALID_ARGUMENT, "plan is NULL");
         Plan &pl = const_cast<axf_plan *>(plan)->pl;
         if (near_pairs) *near_pairs = pl.near_pairs;
         if (s2l_pairs) *s2l_pairs = pl.s2l_pairs;
+        if (s2l_units) *s2l_units = pl.s2l_units;
         if (flops) {
             if (!pl.census_done) {
                 AXF_HIP(hipSetDevice(pl.device));
@@ -440,7 +442,9 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
             flops[AXF_PHASE_P2M] = (double)pl.src.n * (4.0 * P * C + 2.0 * P);
             // separable shifts: M2M 4 children in z + 2 parities in r, L2L r then z
             flops[AXF_PHASE_M2M] = nbox_up * C * c3 * 24.0;
-            flops[AXF_PHASE_S2L] = (double)pl.s2l_pairs * C * P * P * 4.0;
+            // one contraction per (target box, offset unit): the offsets
+            // (dr, dz) and (dr, -dz) share it
+            flops[AXF_PHASE_S2L] = (double)pl.s2l_units * C * P * P * 4.0;
             flops[AXF_PHASE_L2L] = nbox_down * C * c3 * 8.0;
             flops[AXF_PHASE_LEAF] = pair_flops(pl.census_near) + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
             flops[AXF_PHASE_DIRECT] = pair_flops(pl.census_direct);

@@ -302,39 +302,41 @@ __global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int3
 }
 
 // ------------------------------------------------------- S2L, tiled form
-// One offset's contraction for one lane: rows i = 0..M of the staged
-// moments against the table row (k, i) of an outward offset or (i, k) of an
-// inward one, from the lane's first column l0 (one row advance per i).  With
+// One offset pair's contraction for one lane: rows i = 0..M of the staged
+// combined moments (the lane's column parity) against the table row (k, i)
+// of an outward offset or (i, k) of an inward one, from the lane's first
+// column l0 (one row advance per i); the lane's columns are l0 + 2u.  With
 // FIX the order is the compile-time MW and every loop is unrolled: each row
-// loads exactly its window (M - i + LB entries) with no branches.  Otherwise
-// the window is read whole (MW + LB entries, M <= MW): entries past c = 2M -
-// k - i + LB - 1 only meet j > M - i, which is skipped, and the table
-// allocation is padded past its last row.
+// loads exactly its window (M - i + 2LB - 1 entries) with no branches.
+// Otherwise the window is read whole (MW + 2LB - 1 entries, M <= MW): entries
+// past c = 2M - k - i only meet columns l > M - k, which are never written,
+// or j > M - i, which is skipped, and the table allocation is padded past its
+// last row.
 template <int LB, int TB, int MW, bool FIX>
 __device__ __forceinline__ void s2l_row(int M, int i, const double *&row, const double2 *&mrow, int k, bool outward,
                                         double2 (&acc)[LB][TB])
 {
-    constexpr int NW = MW + LB;
+    constexpr int NW = MW + 2 * LB - 1;
     const int jn = M - i;
     double w[NW];
 #pragma unroll
     for (int q = 0; q < NW; ++q)
-        if (!FIX || q < jn + LB) w[q] = row[q];
+        if (!FIX || q < jn + 2 * LB - 1) w[q] = row[q];
 #pragma unroll
     for (int j = 0; j <= MW; ++j) {
         if (j <= jn) {
 #pragma unroll
             for (int b = 0; b < TB; ++b) {
-                const double2 sv = mrow[j * TB + b];
+                const double2 sv = mrow[j * 2 * TB + b];
 #pragma unroll
                 for (int u = 0; u < LB; ++u) {
-                    acc[u][b].x = fma(w[j + u], sv.x, acc[u][b].x);
-                    acc[u][b].y = fma(w[j + u], sv.y, acc[u][b].y);
+                    acc[u][b].x = fma(w[j + 2 * u], sv.x, acc[u][b].x);
+                    acc[u][b].y = fma(w[j + 2 * u], sv.y, acc[u][b].y);
                 }
             }
         }
     }
-    mrow += (jn + 1) * TB;
+    mrow += (jn + 1) * 2 * TB;
     // next row: (k, i + 1) is 2M + 1 - k - i entries on, (i + 1, k) one
     // a-slab of the table less the rows b < k of slab i and b >= k of slab i + 1
     row += outward ? 2 * M + 1 - k - i : (M + 1) * (2 * M + 1) - (M * (M + 1)) / 2 - k - (M + 1) * i;
@@ -345,7 +347,7 @@ __device__ __forceinline__ void s2l_rows(int M, const double *__restrict__ T, in
                                          const double2 *ms, double2 (&acc)[LB][TB])
 {
     const double *row = T + (outward ? table_row(M, k, 0) : table_row(M, 0, k)) + l0;
-    const double2 *mrow = ms;
+    const double2 *mrow = ms + (l0 & 1) * TB;
     if constexpr (FIX) {
 #pragma unroll
         for (int i = 0; i <= MW; ++i) s2l_row<LB, TB, MW, true>(MW, i, row, mrow, k, outward, acc);
@@ -359,14 +361,19 @@ __device__ __forceinline__ void s2l_rows(int M, const double *__restrict__ T, in
 // target boxes of one radial station with the same z parity, so that every
 // box of the tile has the same interaction-list offsets (dr, dz) and
 // therefore, for each offset, the same operator: one table, one
-// orientation.  Each lane owns the outputs (k, l0 .. l0+LB-1) of all TB
-// boxes (the W waves split the output rows between them, so the table is
-// not read twice); for each input moment (i, j) the table values T[k][i][j+l]
-// of the lane's outputs form a window that slides by one entry per j (Hankel
-// structure), so each step loads one table value and does 2 LB TB FMAs on
-// moments broadcast from LDS.  The forward sign (-1)^(j+l) is split into
-// (-1)^j on the staged moments and (-1)^l on the accumulators.  The result,
-// times (-1)^l / l!, is added to the locals that the L2L pass initialised.
+// orientation.  The offsets (dr, dz) and (dr, -dz) share the table of |dz|
+// and differ only by the sign (-1)^(j+l) of the forward one (z_target >
+// z_source), so they are taken together: with M+ the moments of the source
+// above and M- those of the source below, the even columns l see A = M+ +
+// (-1)^j M- and the odd ones B = M+ - (-1)^j M-, one contraction for both
+// (18 such units per tile instead of 27 offsets).  Each lane owns the outputs
+// (k, l0 + 2u), u < LB, of one column parity for all TB boxes (the W waves
+// split the output rows between them, so the table is not read twice); for
+// each input moment (i, j) the table values T[k][i][j+l] of the lane's
+// outputs form a window that slides by one entry per j (Hankel structure),
+// so each step loads one table value and does 2 LB TB FMAs on combined
+// moments broadcast from LDS.  The result, times (-1)^l / l!, is added to the
+// locals that the L2L pass initialised.
 // Compiled S2L shapes: (LB, MW, FIX) with MW = M rounded up to a multiple
 // of 4, the window bound, LB from the slot rule, and FIX = (M == MW): the
 // fully unrolled rows of a compile-time order.
@@ -403,7 +410,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                                                  double2 *__restrict__ loc, int item, int G,
                                                  double2 *__restrict__ part, int nocc)
 {
-    extern __shared__ double2 ms[];          // [P][TB] staged moments, boxes interleaved
+    extern __shared__ double2 ms[];          // [P][2][TB] combined moments A, B; boxes interleaved
     __shared__ double invfact[AXF_MAX_ORDER + 1];
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
@@ -420,18 +427,20 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
         for (int t = 2; t <= tid; ++t) f *= t;
         invfact[tid] = 1.0 / f;
     }
-    // this lane's outputs: row k, columns l0 .. l0 + LB - 1
+    // this lane's outputs: row k, columns l0 + 2u (u < LB) of one parity;
+    // per row the even columns come first, then the odd ones
     int k = 0, l0 = 0, acc_lane = tid;
     bool live = false;
     for (int kk = 0; kk <= M; ++kk) {
-        int nblk = (M + 1 - kk + LB - 1) / LB;
-        if (acc_lane < nblk) {
+        const int ncol = M + 1 - kk;
+        const int ne = ((ncol + 1) / 2 + LB - 1) / LB, no = (ncol / 2 + LB - 1) / LB;
+        if (acc_lane < ne + no) {
             k = kk;
-            l0 = acc_lane * LB;
+            l0 = acc_lane < ne ? 2 * LB * acc_lane : 1 + 2 * LB * (acc_lane - ne);
             live = true;
             break;
         }
-        acc_lane -= nblk;
+        acc_lane -= ne + no;
     }
     int zb[TB], sl[TB];
 #pragma unroll
@@ -449,59 +458,51 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
     const int par = tl.y;                       // z parity of the tile
     const int dr0 = -2 - (station & 1), dz0 = -2 - par;
     const double *tab_n = tab + (size_t)n * TS;
-    int oc = 0;                                 // index of the offset in the interaction list
+    int oc = 0;                                 // index of the unit in the interaction list
     for (int dr = dr0; dr < dr0 + 6; ++dr) {
         const int jr = station + dr;
-        for (int dz = dz0; dz < dz0 + 6; ++dz) {
-            if (dr >= -1 && dr <= 1 && dz >= -1 && dz <= 1) continue;
-            if (oc++ % G != g || jr < 0 || jr >= nb) continue;   // another group's offset
-            int ss[TB];
+        const bool near_r = dr >= -1 && dr <= 1;
+        for (int adz = 0; adz <= 3; ++adz) {
+            // the unit's offsets dz = +adz (source above the target) and
+            // dz = -adz (below: forward), each if it is in the interaction
+            // list (children of the parent's neighbours, not adjacent)
+            const bool hasp = adz > 0 && adz <= dz0 + 5 && !(near_r && adz <= 1);
+            const bool hasm = -adz >= dz0 && !(near_r && adz <= 1);
+            if (!hasp && !hasm) continue;
+            if (oc++ % G != g || jr < 0 || jr >= nb) continue;   // another group's unit
+            int sp[TB], sm[TB];
             bool any = false;
 #pragma unroll
             for (int b = 0; b < TB; ++b) {
-                int jz = zb[b] + dz;
-                ss[b] = (sl[b] >= 0 && jz >= 0 && jz < nb) ? sslot[jr * nb + jz] : -1;
-                any |= ss[b] >= 0;
+                const int jp = zb[b] + adz, jm = zb[b] - adz;
+                sp[b] = (hasp && sl[b] >= 0 && jp < nb) ? sslot[jr * nb + jp] : -1;
+                sm[b] = (hasm && sl[b] >= 0 && jm >= 0) ? sslot[jr * nb + jm] : -1;
+                any |= sp[b] >= 0 || sm[b] >= 0;
             }
             if (!any) continue;
             const bool outward = dr <= 0;               // target radius >= source radius
-            const bool fwd = dz <= 0;                   // z_target >= z_source
             const int inner = outward ? jr : station;
-            const int adr = outward ? -dr : dr, adz = dz < 0 ? -dz : dz;
+            const int adr = outward ? -dr : dr;
             const double *T = tab_n + ((size_t)inner * 12 + geom_slot(adr, adz)) * nmodes * (size_t)TS;
             __syncthreads();
             for (int e = tid; e < TB * P; e += nthr) {
-                int b = e / P, p = e - b * P;
-                double2 v = make_double2(0.0, 0.0);
-                if (ss[b] >= 0) v = mom[((int64_t)ss[b] * C + c) * P + p];
-                if (fwd) {
-                    int i = 0, q = p;
+                const int b = e / P, p = e - b * P;
+                double2 vp = make_double2(0.0, 0.0), vm = make_double2(0.0, 0.0);
+                if (sp[b] >= 0) vp = mom[((int64_t)sp[b] * C + c) * P + p];
+                if (sm[b] >= 0) {
+                    vm = mom[((int64_t)sm[b] * C + c) * P + p];
+                    int i = 0, q = p;               // q = j of the moment (i, j)
                     while (q >= M + 1 - i) {
                         q -= M + 1 - i;
                         ++i;
                     }
-                    if (q & 1) v = make_double2(-v.x, -v.y);
+                    if (q & 1) vm = make_double2(-vm.x, -vm.y);
                 }
-                ms[p * TB + b] = v;
+                ms[(p * 2) * TB + b] = make_double2(vp.x + vm.x, vp.y + vm.y);
+                ms[(p * 2 + 1) * TB + b] = make_double2(vp.x - vm.x, vp.y - vm.y);
             }
             __syncthreads();
-            if (fwd) {
-#pragma unroll
-                for (int u = 0; u < LB; ++u)
-                    if ((l0 + u) & 1)
-#pragma unroll
-                        for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
-            }
-            if (live) {
-                s2l_rows<LB, TB, MW, FIX>(FIX ? MW : M, T, k, l0, outward, ms, acc);
-            }
-            if (fwd) {
-#pragma unroll
-                for (int u = 0; u < LB; ++u)
-                    if ((l0 + u) & 1)
-#pragma unroll
-                        for (int b = 0; b < TB; ++b) acc[u][b] = make_double2(-acc[u][b].x, -acc[u][b].y);
-            }
+            if (live) s2l_rows<LB, TB, MW, FIX>(FIX ? MW : M, T, k, l0, outward, ms, acc);
         }
     }
     __syncthreads();                            // invfact is visible even when no offset ran
@@ -512,7 +513,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
         if (!live || sl[b] < 0) continue;
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
-            const int ll = l0 + u;
+            const int ll = l0 + 2 * u;
             if (ll > M - k) continue;
             const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
             const int64_t e = ((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll);
@@ -1051,7 +1052,7 @@ SideView view_of(const Side &s)
 template <int LB, int TB, int MW, bool FIX>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
-    size_t shm = sizeof(double2) * (size_t)TB * pl.P;
+    size_t shm = sizeof(double2) * 2 * (size_t)TB * pl.P;
     const int G = tgt.s2l_groups[l];
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
     k_s2l_tile<LB, TB, MW, FIX><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
@@ -1209,7 +1210,7 @@ template <int LB, int TB, int MW, bool FIX>
 void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
 {
     const int P = (bq.M + 1) * (bq.M + 2) / 2;
-    size_t shm = sizeof(double2) * (size_t)TB * P;
+    size_t shm = sizeof(double2) * 2 * (size_t)TB * P;
     int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
     kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }

@@ -99,13 +99,17 @@ struct Side {
 };
 
 // Shape of the tiled S2L: output slots of one (box, channel) are rows k
-// split into blocks of LB columns; LB is the smallest width whose slots fit
-// in four waves, the block has one wave per 64 slots, and a tile holds TB
-// target boxes (4: measured best against 2, 8 and 16 at M = 24).
+// whose even and odd columns are each split into blocks of LB (columns l0,
+// l0 + 2, ...); LB is the smallest width whose slots fit in four waves, the
+// block has one wave per 64 slots, and a tile holds TB target boxes (4:
+// measured best against 2, 8 and 16 at M = 24).
 inline int s2l_slots(int M, int lb)
 {
     int s = 0;
-    for (int k = 0; k <= M; ++k) s += (M + 1 - k + lb - 1) / lb;
+    for (int k = 0; k <= M; ++k) {
+        const int ncol = M + 1 - k;
+        s += ((ncol + 1) / 2 + lb - 1) / lb + (ncol / 2 + lb - 1) / lb;
+    }
     return s;
 }
 inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
@@ -114,7 +118,7 @@ inline int s2l_tb(int) { return 4; }
 // Window bound of the S2L lanes: M rounded up to a multiple of 4.
 inline int s2l_window(int M) { return M <= 4 ? 4 : (M + 3) / 4 * 4; }
 // Doubles past the last table: a lane reads its whole window, up to
-// s2l_window + s2l_lb - 1 entries past the start of the table's last row.
+// s2l_window + 2 s2l_lb - 1 entries past the start of the table's last row.
 constexpr size_t kTablePad = 64;
 // Offset groups of a level: the 27 interaction-list offsets of a (tile,
 // channel) are split over G blocks so that a level launches ~2048 waves.
@@ -158,7 +162,7 @@ struct Plan {
     double *gsum = nullptr;     // adjoint coordinate-gradient scratch
     double *tab_scratch = nullptr;
     Arena points, tree, expn, tilemem;
-    int64_t near_pairs = 0, s2l_pairs = 0;
+    int64_t near_pairs = 0, s2l_pairs = 0, s2l_units = 0;   // S2L: box pairs, (box, offset unit) pairs
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
     size_t device_bytes = 0;

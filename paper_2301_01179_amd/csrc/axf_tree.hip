@@ -336,14 +336,29 @@ __global__ void k_count_s2l(const int32_t *__restrict__ tbox, int nocc, const in
     int nb = 1 << level;
     int b = tbox[k];
     int ir = b / nb, iz = b - ir * nb;
-    int c = 0;
-    for (int jr = 2 * (ir >> 1) - 2; jr < 2 * (ir >> 1) + 4; ++jr)
-        for (int jz = 2 * (iz >> 1) - 2; jz < 2 * (iz >> 1) + 4; ++jz) {
-            if (jr < 0 || jz < 0 || jr >= nb || jz >= nb) continue;
-            if (abs(jr - ir) <= 1 && abs(jz - iz) <= 1) continue;
-            if (sslot[jr * nb + jz] >= 0) ++c;
+    const int zlo = 2 * (iz >> 1) - 2, zhi = 2 * (iz >> 1) + 4;   // z window of the list
+    int c = 0, u = 0;
+    for (int jr = 2 * (ir >> 1) - 2; jr < 2 * (ir >> 1) + 4; ++jr) {
+        if (jr < 0 || jr >= nb) continue;
+        const bool near_r = abs(jr - ir) <= 1;
+        // offset units: source boxes at z distance +adz and -adz share one
+        // contraction; a unit counts if either of its boxes is occupied
+        for (int adz = 0; adz <= 3; ++adz) {
+            if (near_r && adz <= 1) continue;
+            bool occ = false;
+            for (int sgn = -1; sgn <= (adz > 0 ? 1 : -1); sgn += 2) {
+                const int jz = iz + sgn * adz;
+                if (jz < zlo || jz >= zhi || jz < 0 || jz >= nb) continue;
+                if (sslot[jr * nb + jz] >= 0) {
+                    ++c;
+                    occ = true;
+                }
+            }
+            u += occ;
         }
+    }
     atomicAdd(out, (unsigned long long)c);
+    atomicAdd(out + 1, (unsigned long long)u);
 }
 
 inline int nblk(int64_t n, int b = kBlk) { return (int)((n + b - 1) / b); }
@@ -596,6 +611,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     AXF_HIP(hipStreamSynchronize(st));
     pl.near_pairs = (int64_t)h_cnt[0];
     pl.s2l_pairs = (int64_t)h_cnt[1];
+    pl.s2l_units = (int64_t)h_cnt[2];
     pl.src.max_leaf = h_small[0];
     pl.fld.max_leaf = h_small[1];
     pl.src.nchunks = h_small[2];

@@ -64,3 +64,40 @@ def test_census_matches_numpy_count():
     assert abs(got["steps"] - ref[3]) <= 1e-3 * ref[3]
     d = plan.census()["direct"]
     assert d["pairs"] == 1500 * 700 - np.sum((rs[:, None] == rf[None, :]) & (zs[:, None] == zf[None, :]))
+
+
+def _s2l_counts(rs, zs, rf, zf, depth):
+    """S2L box pairs and units counted in numpy on the plan's tree: for each
+    occupied target box of levels 2..depth, the occupied source boxes among
+    the children of its parent's neighbours that are not adjacent to it
+    (section 2.2); a unit is the offset pair (dr, +adz), (dr, -adz)."""
+    rlo, zlo, L, invL = O.square_info(rs, zs, rf, zf)
+    isr, isz = O.box_indices(rs, zs, rlo, zlo, invL, depth)
+    ifr, ifz = O.box_indices(rf, zf, rlo, zlo, invL, depth)
+    pairs = units = 0
+    for lev in range(2, depth + 1):
+        sh = depth - lev
+        src = set(zip((isr >> sh).tolist(), (isz >> sh).tolist()))
+        for ir, iz in set(zip((ifr >> sh).tolist(), (ifz >> sh).tolist())):
+            for jr in range(2 * (ir // 2) - 2, 2 * (ir // 2) + 4):
+                by_adz = {}
+                for jz in range(2 * (iz // 2) - 2, 2 * (iz // 2) + 4):
+                    if abs(jr - ir) <= 1 and abs(jz - iz) <= 1:
+                        continue
+                    if (jr, jz) in src:
+                        pairs += 1
+                        by_adz[abs(jz - iz)] = True
+                units += len(by_adz)
+    return pairs, units
+
+
+@gpu
+def test_s2l_pair_and_unit_counts():
+    need_gpu()
+    from paper_2301_01179_amd import axf
+    rs, zs, rf, zf, _ = inputs.annulus(3000, 2000, 3, seed=4)
+    for depth in (3, 5):
+        plan = axf.Plan(rs, zs, rf, zf, 3, 6, depth=depth)
+        w = plan.work()
+        assert (w["s2l_pairs"], w["s2l_units"]) == _s2l_counts(rs, zs, rf, zf, depth)
+        assert w["s2l_units"] < w["s2l_pairs"]

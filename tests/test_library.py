@@ -71,10 +71,23 @@ def test_null_and_size_errors():
 def test_mode_buckets_and_tile_widths_cover_limits():
     """Host-side launch shapes of the tiled S2L (mirror of the rule in the
     library): up to the maximum order the output slots of one (box, channel)
-    fit in at most four waves with blocks of at most two columns."""
+    -- per row, the even and the odd columns in blocks of lb -- fit in at
+    most four waves with blocks of at most two columns, and every output
+    (k, l) has exactly one slot."""
     import math
+
+    def slot_cols(M, b):
+        cols = []
+        for k in range(M + 1):
+            ncol = M + 1 - k
+            for par in (0, 1):
+                own = list(range(par, ncol, 2))
+                cols += [(k, own[i:i + b]) for i in range(0, len(own), b)]
+        return cols
+
     for M in range(0, 25):
-        lb = next(b for b in range(1, 4)
-                  if sum(math.ceil((M + 1 - k) / b) for k in range(M + 1)) <= 256)
-        slots = sum(math.ceil((M + 1 - k) / lb) for k in range(M + 1))
-        assert lb <= 2 and math.ceil(slots / 64) <= 4
+        lb = next(b for b in range(1, 4) if len(slot_cols(M, b)) <= 256)
+        cols = slot_cols(M, lb)
+        assert lb <= 2 and math.ceil(len(cols) / 64) <= 4
+        owned = sorted((k, l) for k, ls in cols for l in ls)
+        assert owned == [(k, l) for k in range(M + 1) for l in range(M + 1 - k)]
