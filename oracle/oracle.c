@@ -600,9 +600,12 @@ static ora_square ora_bounding_square(int64_t ns, const double *rs, const double
         zmin = fmin(zmin, zf[j]); zmax = fmax(zmax, zf[j]);
     }
     ora_square sq;
-    sq.rlo = rmin;
-    sq.zlo = zmin;
     double ext = fmax(rmax - rmin, zmax - zmin);
+    /* side = the larger extent; in r the square starts on the axis (the
+       paper's domain 0 <= r <= r_max) whenever that side still reaches r_max,
+       else at the smallest radius */
+    sq.rlo = rmax <= ext ? 0.0 : rmin;
+    sq.zlo = zmin;
     sq.L = ext > 0.0 ? ext : 1.0;
     sq.invL = 1.0 / sq.L;
     return sq;

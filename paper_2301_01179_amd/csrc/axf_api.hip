@@ -172,7 +172,11 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
         sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
-    size_t ngeom = 12 * (((size_t)1 << (d + 1)) - 4);
+    // with the square on the axis the stations of every level sit at the
+    // same box-unit radii (s + 1/2), so a level's tables are the finest
+    // level's first stations times 2^(l-d): only those are stored
+    const bool shared = pl.rlo == 0.0;
+    size_t ngeom = shared ? 12 * ((size_t)1 << d) : 12 * (((size_t)1 << (d + 1)) - 4);
     sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
     sz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     // offset groups of the S2L pass and their partial-sum buffer (one level
@@ -194,8 +198,10 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
     double *tab = pl.expn.take<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
-    for (int l = 2; l <= d; ++l)
-        pl.lev[l].tab = tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
+    for (int l = 2; l <= d; ++l) {
+        pl.lev[l].tab = shared ? tab : tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
+        pl.lev[l].tscale = shared ? std::ldexp(1.0, l - d) : 1.0;
+    }
     pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     pl.s2l_part = pl.expn.take<double2>(std::max<size_t>(part, 1));
     build_tables(pl, st);
@@ -372,6 +378,7 @@ axf_status axf_plan_table(const axf_plan *plan, int32_t level, int32_t station, 
                 for (int b = 0; b <= M; ++b)
                     for (int c = 0; c <= K; ++c) {
                         double v = (a + b + c <= K) ? buf[(size_t)n * TS + table_row(M, a, b) + c] : 0.0;
+                        v *= pl.lev[level].tscale;
                         host_out[(((size_t)n * (M + 1) + a) * (M + 1) + b) * (K + 1) + c] = v;
                     }
     })

@@ -408,7 +408,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
                                                  const double2 *__restrict__ mom,
                                                  const double *__restrict__ tab,
                                                  double2 *__restrict__ loc, int item, int G,
-                                                 double2 *__restrict__ part, int nocc)
+                                                 double2 *__restrict__ part, int nocc, double tscale)
 {
     extern __shared__ double2 ms[];          // [P][2][TB] combined moments A, B; boxes interleaved
     __shared__ double invfact[AXF_MAX_ORDER + 1];
@@ -515,7 +515,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
         for (int u = 0; u < LB; ++u) {
             const int ll = l0 + 2 * u;
             if (ll > M - k) continue;
-            const double f = ((ll & 1) ? -1.0 : 1.0) * invfact[ll];
+            const double f = ((ll & 1) ? -tscale : tscale) * invfact[ll];
             const int64_t e = ((int64_t)sl[b] * C + c) * P + tri_index(M, k, ll);
             if (part) {
                 part[(int64_t)g * nocc * C * P + e] = make_double2(f * acc[u][b].x, f * acc[u][b].y);
@@ -551,10 +551,10 @@ __global__ __launch_bounds__(256) void k_s2l_tile(int M, int nmodes, int nrhs, i
                                                   const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
                                                   const double2 *__restrict__ mom, const double *__restrict__ tab,
                                                   double2 *__restrict__ loc, int G, double2 *__restrict__ part,
-                                                  int nocc)
+                                                  int nocc, double tscale)
 {
     s2l_tile_body<LB, TB, MW, FIX>(M, nmodes, nrhs, level, TS, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G,
-                          part, nocc);
+                                   part, nocc, tscale);
 }
 
 // ------------------------------------------------------------ pair sums
@@ -1057,7 +1057,7 @@ void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
     k_s2l_tile<LB, TB, MW, FIX><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
         pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],
-        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l]);
+        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l], pl.lev[l].tscale);
     if (G > 1) {
         const int64_t n = (int64_t)tgt.nocc[l] * pl.C * pl.P;
         k_s2l_reduce<<<(int)((n + 255) / 256), 256, 0, st>>>(n, G, part, pl.lev[l].loc);
@@ -1175,7 +1175,7 @@ __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, con
         const ProbDev &pd = P[it.x];
         __syncthreads();
         s2l_tile_body<LB, TB, MW, FIX>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
-                              pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0);
+                              pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0, pd.tscale[l]);
     }
 }
 
@@ -1433,6 +1433,7 @@ void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd)
         pd.mom[l] = pl.lev[l].mom;
         pd.loc[l] = pl.lev[l].loc;
         pd.tab[l] = pl.lev[l].tab;
+        pd.tscale[l] = pl.lev[l].tscale;
     }
     pd.chunks = pl.fld.chunks;
 }

@@ -136,6 +136,7 @@ struct Level {
     double2 *mom = nullptr;    // [max(nocc)][C][P] moments (z-factorial normalised)
     double2 *loc = nullptr;    // [max(nocc)][C][P] local coefficients
     double *tab = nullptr;     // [nb][12][n_modes][TS] S2L tables (x >= 0, outer >= inner)
+    double tscale = 1.0;       // factor of the stored tables (2^(l-d) when levels share the finest's)
 };
 
 // Mode counts the near-field kernels are compiled for; a plan uses the
@@ -231,6 +232,7 @@ struct ProbDev {
     const int32_t *tile_slots[AXF_MAX_DEPTH + 1] = {};
     double2 *mom[AXF_MAX_DEPTH + 1] = {}, *loc[AXF_MAX_DEPTH + 1] = {};
     const double *tab[AXF_MAX_DEPTH + 1] = {};
+    double tscale[AXF_MAX_DEPTH + 1] = {};
     const int4 *chunks = nullptr;
 };
 

@@ -384,9 +384,10 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
 void build_tables(Plan &pl, hipStream_t st)
 {
     const int M = pl.M, K = 2 * M, nm = pl.nmodes;
-    // geometry list in storage order: level, station, slot
+    // geometry list in storage order: level, station, slot (only the finest
+    // level when the levels share its tables: square on the axis)
     std::vector<GeomDesc> geoms;
-    for (int l = 2; l <= pl.d; ++l) {
+    for (int l = pl.rlo == 0.0 ? pl.d : 2; l <= pl.d; ++l) {
         int nb = 1 << l;
         double h = pl.L / nb;
         for (int s = 0; s < nb; ++s)
