@@ -412,6 +412,7 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
 {
     extern __shared__ double2 ms[];          // [P][2][TB] combined moments A, B; boxes interleaved
     __shared__ double invfact[AXF_MAX_ORDER + 1];
+    __shared__ double jsign[(AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 2) / 2];   // (-1)^j of moment p = (i, j)
     const int P = (M + 1) * (M + 2) / 2;
     const int C = nmodes * nrhs;
     const int ti = item / (C * G), rem = item - ti * (C * G);
@@ -426,6 +427,14 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
         double f = 1.0;
         for (int t = 2; t <= tid; ++t) f *= t;
         invfact[tid] = 1.0 / f;
+    }
+    for (int p = tid; p < P; p += nthr) {
+        int i = 0, q = p;                       // q = j of the moment (i, j)
+        while (q >= M + 1 - i) {
+            q -= M + 1 - i;
+            ++i;
+        }
+        jsign[p] = (q & 1) ? -1.0 : 1.0;
     }
     // this lane's outputs: row k, columns l0 + 2u (u < LB) of one parity;
     // per row the even columns come first, then the odd ones
@@ -485,21 +494,21 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
             const int adr = outward ? -dr : dr;
             const double *T = tab_n + ((size_t)inner * 12 + geom_slot(adr, adz)) * nmodes * (size_t)TS;
             __syncthreads();
-            for (int e = tid; e < TB * P; e += nthr) {
-                const int b = e / P, p = e - b * P;
-                double2 vp = make_double2(0.0, 0.0), vm = make_double2(0.0, 0.0);
-                if (sp[b] >= 0) vp = mom[((int64_t)sp[b] * C + c) * P + p];
-                if (sm[b] >= 0) {
-                    vm = mom[((int64_t)sm[b] * C + c) * P + p];
-                    int i = 0, q = p;               // q = j of the moment (i, j)
-                    while (q >= M + 1 - i) {
-                        q -= M + 1 - i;
-                        ++i;
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                const double2 *mp = sp[b] >= 0 ? mom + ((int64_t)sp[b] * C + c) * P : nullptr;
+                const double2 *mm = sm[b] >= 0 ? mom + ((int64_t)sm[b] * C + c) * P : nullptr;
+                for (int p = tid; p < P; p += nthr) {
+                    double2 vp = make_double2(0.0, 0.0), vm = make_double2(0.0, 0.0);
+                    if (mp) vp = mp[p];
+                    if (mm) {
+                        const double2 v = mm[p];
+                        const double sg = jsign[p];
+                        vm = make_double2(sg * v.x, sg * v.y);
                     }
-                    if (q & 1) vm = make_double2(-vm.x, -vm.y);
+                    ms[(p * 2) * TB + b] = make_double2(vp.x + vm.x, vp.y + vm.y);
+                    ms[(p * 2 + 1) * TB + b] = make_double2(vp.x - vm.x, vp.y - vm.y);
                 }
-                ms[(p * 2) * TB + b] = make_double2(vp.x + vm.x, vp.y + vm.y);
-                ms[(p * 2 + 1) * TB + b] = make_double2(vp.x - vm.x, vp.y - vm.y);
             }
             __syncthreads();
             if (live) s2l_rows<LB, TB, MW, FIX>(FIX ? MW : M, T, k, l0, outward, ms, acc);

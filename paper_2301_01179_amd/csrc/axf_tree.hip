@@ -1,6 +1,7 @@
 // axf_tree.hip -- uniform (r, z) quadtree on the device (Algorithm 1, first
 // two steps): bounding square, depth, Morton keys, stable radix sort of both
 // point sets, leaf offsets, occupied-box slots per level and leaf work chunks.
+#include <cstring>
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -628,62 +629,75 @@ void build_tiles(Plan &pl, hipStream_t st)
 {
     const int TB = s2l_tb(pl.M);
     Side *sides[2] = {&pl.src, &pl.fld};
+    constexpr int NL = AXF_MAX_DEPTH + 1;
+    // every level's box list of both sides in one copy and one wait
     std::vector<int32_t> hb;
-    std::vector<std::vector<int4>> tiles(2 * (AXF_MAX_DEPTH + 1));
-    std::vector<std::vector<int32_t>> slots(2 * (AXF_MAX_DEPTH + 1));
-    size_t bytes = 0;
-    for (int si = 0; si < 2; ++si) {
-        Side &s = *sides[si];
+    size_t hoff[2][NL] = {}, total = 0;
+    for (int si = 0; si < 2; ++si)
         for (int l = 2; l <= pl.d; ++l) {
-            int n = s.nocc[l];
-            hb.resize(n);
-            if (n) AXF_HIP(hipMemcpyAsync(hb.data(), s.box[l], n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            AXF_HIP(hipStreamSynchronize(st));
+            hoff[si][l] = total;
+            total += sides[si]->nocc[l];
+        }
+    hb.resize(std::max<size_t>(total, 1));
+    for (int si = 0; si < 2; ++si)
+        for (int l = 2; l <= pl.d; ++l)
+            if (sides[si]->nocc[l])
+                AXF_HIP(hipMemcpyAsync(hb.data() + hoff[si][l], sides[si]->box[l],
+                                       sides[si]->nocc[l] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<int4>> tiles(2 * NL);
+    std::vector<std::vector<int32_t>> slots(2 * NL);
+    for (int si = 0; si < 2; ++si) {
+        for (int l = 2; l <= pl.d; ++l) {
+            const int n = sides[si]->nocc[l];
+            const int32_t *bx = hb.data() + hoff[si][l];
             const int nb = 1 << l;
-            auto &tv = tiles[si * (AXF_MAX_DEPTH + 1) + l];
-            auto &sv = slots[si * (AXF_MAX_DEPTH + 1) + l];
+            auto &tv = tiles[si * NL + l];
+            auto &sv = slots[si * NL + l];
             // boxes are station-major in slot order; split each station by parity
             int k = 0;
             while (k < n) {
-                int station = hb[k] / nb, e = k;
-                while (e < n && hb[e] / nb == station) ++e;
+                int station = bx[k] / nb, e = k;
+                while (e < n && bx[e] / nb == station) ++e;
                 for (int par = 0; par < 2; ++par) {
                     int first = (int)sv.size();
                     for (int j = k; j < e; ++j)
-                        if (((hb[j] - station * nb) & 1) == par) sv.push_back(j);
+                        if (((bx[j] - station * nb) & 1) == par) sv.push_back(j);
                     for (int f = first; f < (int)sv.size(); f += TB)
                         tv.push_back(make_int4(station, par, f, std::min(TB, (int)sv.size() - f)));
                 }
                 k = e;
             }
-            bytes += tv.size() * sizeof(int4) + sv.size() * sizeof(int32_t) + 512;
         }
     }
     Sizer sz;
     for (int si = 0; si < 2; ++si)
         for (int l = 2; l <= pl.d; ++l) {
-            sz.add<int4>(std::max<size_t>(1, tiles[si * (AXF_MAX_DEPTH + 1) + l].size()));
-            sz.add<int32_t>(std::max<size_t>(1, slots[si * (AXF_MAX_DEPTH + 1) + l].size()));
+            sz.add<int4>(std::max<size_t>(1, tiles[si * NL + l].size()));
+            sz.add<int32_t>(std::max<size_t>(1, slots[si * NL + l].size()));
         }
     pl.tilemem = arena_acquire(sz.bytes + 4096);
+    // the arena's image on the host, filled in place and copied once
+    std::vector<char> img(sz.bytes + 4096);
     for (int si = 0; si < 2; ++si) {
         Side &s = *sides[si];
         for (int l = 2; l <= pl.d; ++l) {
-            auto &tv = tiles[si * (AXF_MAX_DEPTH + 1) + l];
-            auto &sv = slots[si * (AXF_MAX_DEPTH + 1) + l];
+            auto &tv = tiles[si * NL + l];
+            auto &sv = slots[si * NL + l];
             s.tiles[l] = pl.tilemem.take<int4>(std::max<size_t>(1, tv.size()));
             s.tile_slots[l] = pl.tilemem.take<int32_t>(std::max<size_t>(1, sv.size()));
             s.ntiles[l] = (int)tv.size();
             if (!tv.empty())
-                AXF_HIP(hipMemcpyAsync(s.tiles[l], tv.data(), tv.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+                std::memcpy(img.data() + ((char *)s.tiles[l] - pl.tilemem.base), tv.data(), tv.size() * sizeof(int4));
             if (!sv.empty())
-                AXF_HIP(hipMemcpyAsync(s.tile_slots[l], sv.data(), sv.size() * sizeof(int32_t),
-                                       hipMemcpyHostToDevice, st));
+                std::memcpy(img.data() + ((char *)s.tile_slots[l] - pl.tilemem.base), sv.data(),
+                            sv.size() * sizeof(int32_t));
         }
     }
-    // the host vectors must outlive the copies
+    if (pl.tilemem.used)
+        AXF_HIP(hipMemcpyAsync(pl.tilemem.base, img.data(), pl.tilemem.used, hipMemcpyHostToDevice, st));
+    // the host image must outlive the copy
     AXF_HIP(hipStreamSynchronize(st));
-    (void)bytes;
 }
 
 }  // namespace axf
