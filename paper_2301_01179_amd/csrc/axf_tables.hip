@@ -106,9 +106,9 @@ __host__ __device__ __forceinline__ dd dd_sqrt(dd a)
     double corr = ((a - x2).hi) / (2.0 * x);
     return dd_fast_sum(x, corr);
 }
-__device__ __forceinline__ dd dd_shfl_xor(dd a, int m) { return {__shfl_xor(a.hi, m), __shfl_xor(a.lo, m)}; }
 
-// Threads of k_tab_start; a mode's partial sums are split over LPM lanes.
+// Threads of k_tab_start; a mode's x-derivative sums are split over LPM
+// lanes (16, or 8 above 32 modes).
 constexpr int kStartThreads = 512;
 __host__ __device__ inline int start_lpm(int nw1)
 {
@@ -160,14 +160,6 @@ __host__ __device__ void green_dd(int N, double r, double r1, double x, double c
     }
 }
 
-// Sum over the LPM lanes of a mode (lanes of one mode are adjacent and
-// inside one wave).
-__device__ __forceinline__ dd lane_reduce(dd s, int lpm)
-{
-    for (int m = 1; m < lpm; m <<= 1) s = s + dd_shfl_xor(s, m);
-    return s;
-}
-
 // Starting columns g_{0,0,k}, g_{1,0,k}, g_{0,1,k}, g_{1,1,k} for all modes of
 // one geometry; out layout [geom][n][4][2M+1].  Coefficients (1/q!) d^q/dx^q
 // of the rational factors: x/rho^2 = (-1)^q Re w^-(q+1) and the companions
@@ -185,6 +177,7 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
        *qm = qp + L, *dp = qm + L, *dm = dp + L;
     dd *g00 = dm + L;                 // [Nw+1][L]
     dd *g01 = g00 + (Nw + 1) * L;     // [Nw+1][L]
+    dd *rinv = g01 + (Nw + 1) * L;    // 1 / (k + 1), k < L
     const GeomDesc gd = geoms[blockIdx.x];
     const double r = gd.rout, r1 = gd.rin, x = gd.x;
     const int tid = threadIdx.x;
@@ -208,6 +201,7 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
     const dd A0 = dd_prod(r, r) - dd_prod(r1, r1) - dd_prod(x, x);
     const dd B0 = dd_prod(r1, r1) - dd_prod(r, r) - dd_prod(x, x);
     for (int q = tid; q <= K; q += blockDim.x) {
+        rinv[q] = dd_d(1.0) / dd_d(q + 1.0);
         dd u1p = q >= 1 ? up[q - 1] : dd_d(0.0), u2p = q >= 2 ? up[q - 2] : dd_d(0.0);
         dd u1m = q >= 1 ? um[q - 1] : dd_d(0.0), u2m = q >= 2 ? um[q - 2] : dd_d(0.0);
         fp[q] = up[q] * x + u1p;
@@ -228,23 +222,42 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
         dp[q] = up[q] * (-2.0 * r1) - cpu * dd_two_sum(r, r1) * 2.0;
         dm[q] = um[q] * (-2.0 * r1) + cmu * dd_two_sum(r, -r1) * 2.0;
     }
-    // x-derivatives, k-outer, n-inner (eq. gfunc:derivatives:x)
-    for (int k = 0; k < K; ++k) {
-        dd s = dd_d(0.0);
-        if (active)
-            for (int q = j; q <= k; q += lpm) {
-                dd a = g00[n * L + k - q], b = g00[nm * L + k - q];
-                s = s + (a + b) * fp[q] + (a - b) * fm[q];
+    // x-derivatives, k-outer, n-inner (eq. gfunc:derivatives:x):
+    //   g_n[k+1] = (n - 1/2)/(k+1) sum_{m<=k} (g_n[m] + g_(n-1)[m]) fp[k-m]
+    //                                        + (g_n[m] - g_(n-1)[m]) fm[k-m].
+    // Lane j of a mode owns the sums s_k, k = j (mod lpm); once the entries
+    // of index m are known every lane adds their terms to its own sums, and
+    // the owner of s_m then publishes g_n[m+1] (no cross-lane reduction).
+    constexpr int kOwn = (2 * AXF_MAX_ORDER + 7) / 8;     // sums per lane (lpm >= 8 up to 64 modes)
+    dd acc[kOwn];
+#pragma unroll
+    for (int u = 0; u < kOwn; ++u) acc[u] = dd_d(0.0);
+    for (int m = 0; m < K; ++m) {
+        if (active) {
+            const dd a = g00[n * L + m], b = g00[nm * L + m];
+            const dd sp = a + b, sm = a - b;
+#pragma unroll
+            for (int u = 0; u < kOwn; ++u) {
+                const int k = j + u * lpm;
+                if (k >= m && k < K) acc[u] = acc[u] + sp * fp[k - m] + sm * fm[k - m];
             }
-        s = lane_reduce(s, lpm);
-        if (active && j == 0) g00[n * L + k + 1] = (s * (n - 0.5)) / dd_d(k + 1.0);
+            // owner of s_m: lane m mod lpm, slot m / lpm
+            if (j == m % lpm) {
+                dd sfin = acc[0];
+#pragma unroll
+                for (int u = 1; u < kOwn; ++u)
+                    if (u == m / lpm) sfin = acc[u];
+                g00[n * L + m + 1] = sfin * (rinv[m] * (n - 0.5));
+            }
+        }
         __syncthreads();
     }
     // r-derivative and its r <-> r1 image: g10 goes out, g01 stays for g11.
-    // Every (mode, k) entry is an independent sum: one thread each.
+    // Every (mode, k) entry is an independent sum of k + 1 terms; a thread
+    // takes the entries k and n - 1 - k of one mode (n entries per mode), so
+    // every thread sums n + 1 terms and a wave's lanes finish together.
     if (M >= 1) {
-        for (int e = tid; e < (Nw + 1) * K; e += blockDim.x) {
-            const int m = e / K, k = e - m * K;
+        auto g10_entry = [&](int m, int k) {
             const int mm = m == 0 ? 1 : m - 1;
             dd s1 = dd_d(0.0), s2 = dd_d(0.0);
             for (int q = 0; q <= k; ++q) {
@@ -256,11 +269,15 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
             const dd g = g00[m * L + k];
             g01[m * L + k] = (s2 * (m - 0.5) - g) / dd_d(2.0 * r1);
             if (m < nmodes) o[((size_t)m * 4 + 1) * L + k] = ((s1 * (m - 0.5) - g) / dd_d(2.0 * r)).hi;
+        };
+        const int h10 = (K + 1) / 2;
+        for (int e = tid; e < (Nw + 1) * h10; e += blockDim.x) {
+            const int m = e / h10, k = e - m * h10;
+            g10_entry(m, k);
+            if (K - 1 - k != k) g10_entry(m, K - 1 - k);
         }
         __syncthreads();
-        for (int e = tid; e < (Nw + 1) * (K - 1); e += blockDim.x) {
-            const int m = e / (K - 1), k = e - m * (K - 1);
-            if (m >= nmodes) continue;
+        auto g11_entry = [&](int m, int k) {
             const int mm = m == 0 ? 1 : m - 1;
             dd s = dd_d(0.0);
             for (int q = 0; q <= k; ++q) {
@@ -269,6 +286,12 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
                 s = s + (a + b) * dp[q] + (e1 + f1) * pp[q] + (a - b) * dm[q] + (e1 - f1) * pm[q];
             }
             o[((size_t)m * 4 + 3) * L + k] = ((s * (m - 0.5) - g01[m * L + k]) / dd_d(2.0 * r)).hi;
+        };
+        const int h11 = K / 2;   // K - 1 entries per mode, paired
+        for (int e = tid; e < nmodes * h11; e += blockDim.x) {
+            const int m = e / h11, k = e - m * h11;
+            g11_entry(m, k);
+            if (K - 2 - k != k) g11_entry(m, K - 2 - k);
         }
     }
     // g00, g01 and the zero tails
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
 size_t start_lds_bytes(int M, int nmodes)
 {
     const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;
-    return sizeof(dd) * (size_t)(2 * M + 1) * (10 + 2 * (Nw + 1));
+    return sizeof(dd) * (size_t)(2 * M + 1) * (11 + 2 * (Nw + 1));
 }
 
 // Laplace recursion for one (geometry, mode); writes the scaled table.
