@@ -128,6 +128,7 @@ void plan_release(Plan *pl)
     arena_release(pl->tree);
     arena_release(pl->expn);
     arena_release(pl->tilemem);
+    arena_release(pl->tabmem);
 }
 
 static void validate_params(const axf_params *p)
@@ -141,6 +142,18 @@ static void validate_params(const axf_params *p)
     AXF_REQUIRE(p->depth != 0 || p->max_leaf >= 1, AXF_ERR_INVALID_ARGUMENT,
                 "max_leaf must be >= 1 when depth is 0");
     AXF_REQUIRE(p->nrhs >= 1 && p->nrhs <= AXF_MAX_RHS, AXF_ERR_UNSUPPORTED, "nrhs must be in 1..8");
+}
+
+// The stream that builds a plan's tables beside the tree (one per device,
+// default priority, created on first use and kept for the process).
+static hipStream_t table_stream(int device)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    hipStream_t &s = streams[device & 63];
+    if (!s) AXF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
 }
 
 // Build everything after the parameters are known valid.
@@ -161,10 +174,38 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     pl.Cs = pl.nmb * p.nrhs;
     pl.src.n = ns;
     pl.fld.n = nf;
-    build_tree(pl, rs, zs, rf, zf, st);
+    // The tables depend only on the square, the depth, the order and the
+    // modes: they are built on a second stream while the tree is sorted and
+    // the S2L tiles are made, and joined before the plan is returned.
+    hipStream_t side = table_stream(pl.device);
+    auto start_tables = [&]() {
+        const int d = pl.d;
+        // with the square on the axis the stations of every level sit at the
+        // same box-unit radii (s + 1/2), so a level's tables are the finest
+        // level's first stations times 2^(l-d): only those are stored
+        const bool shared = pl.rlo == 0.0;
+        const size_t ngeom = shared ? 12 * ((size_t)1 << d) : 12 * (((size_t)1 << (d + 1)) - 4);
+        Sizer tz;
+        tz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
+        tz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+        pl.tabmem = arena_acquire(tz.bytes + 4096);
+        double *tab = pl.tabmem.take<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
+        for (int l = 2; l <= d; ++l) {
+            pl.lev[l].tab = shared ? tab : tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
+            pl.lev[l].tscale = shared ? std::ldexp(1.0, l - d) : 1.0;
+        }
+        pl.tab_scratch = pl.tabmem.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+        // after everything the caller's stream already holds
+        hipEvent_t ev = event_get(pl);
+        AXF_HIP(hipEventRecord(ev, st));
+        AXF_HIP(hipStreamWaitEvent(side, ev, 0));
+        pl.spare_events.push_back(ev);   // reusable: the wait has been enqueued
+        build_tables(pl, side);
+    };
+    build_tree(pl, rs, zs, rf, zf, st, start_tables);
     build_tiles(pl, st);
 
-    // expansion arena: moments, locals, tables, table scratch
+    // expansion arena: moments, locals and the S2L partial sums
     const int d = pl.d;
     Sizer sz;
     for (int l = 2; l <= d; ++l) {
@@ -172,13 +213,6 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
         sz.add<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
-    // with the square on the axis the stations of every level sit at the
-    // same box-unit radii (s + 1/2), so a level's tables are the finest
-    // level's first stations times 2^(l-d): only those are stored
-    const bool shared = pl.rlo == 0.0;
-    size_t ngeom = shared ? 12 * ((size_t)1 << d) : 12 * (((size_t)1 << (d + 1)) - 4);
-    sz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
-    sz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     // offset groups of the S2L pass and their partial-sum buffer (one level
     // at a time, either side as targets)
     size_t part = 0;
@@ -197,15 +231,12 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].mom = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
         pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
-    double *tab = pl.expn.take<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
-    for (int l = 2; l <= d; ++l) {
-        pl.lev[l].tab = shared ? tab : tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
-        pl.lev[l].tscale = shared ? std::ldexp(1.0, l - d) : 1.0;
-    }
-    pl.tab_scratch = pl.expn.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
     pl.s2l_part = pl.expn.take<double2>(std::max<size_t>(part, 1));
-    build_tables(pl, st);
-    pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes;
+    // join: the tables are complete before the plan is used on any stream
+    AXF_HIP(hipStreamSynchronize(side));
+    pl.geom_host.clear();
+    pl.geom_host.shrink_to_fit();
+    pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes + pl.tabmem.bytes;
 }
 
 }  // namespace axf

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "axf.h"
@@ -162,7 +163,8 @@ struct Plan {
     double2 *s2l_part = nullptr;  // partial S2L sums of the offset groups of one level
     double *gsum = nullptr;     // adjoint coordinate-gradient scratch
     double *tab_scratch = nullptr;
-    Arena points, tree, expn, tilemem;
+    Arena points, tree, expn, tilemem, tabmem;
+    std::vector<double> geom_host;   // table geometries (4 doubles each) until the tables are built
     int64_t near_pairs = 0, s2l_pairs = 0, s2l_units = 0;   // S2L: box pairs, (box, offset unit) pairs
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
@@ -190,8 +192,10 @@ struct PhaseTimer {
 // -------------------------------------------------------------- launchers
 hipEvent_t event_get(Plan &pl);
 // tree (axf_tree.hip)
+// `after_depth` runs once the square and the depth are known (before the
+// sort), so that work depending only on them can start.
 void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, const double *zf,
-                hipStream_t st);
+                hipStream_t st, const std::function<void()> &after_depth);
 void build_tiles(Plan &pl, hipStream_t st);
 // tables (axf_tables.hip)
 void build_tables(Plan &pl, hipStream_t st);

@@ -14,6 +14,7 @@
 // columns b <= 1 and then in r1 for all a.  (The paper's form, divided by r,
 // is the Leibniz expansion of 1/r and 1/r^2; its printed version lacks the
 // axial term (k+1)(k+2) g_{i,j,k+2}.)
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -408,7 +409,8 @@ void build_tables(Plan &pl, hipStream_t st)
 {
     const int M = pl.M, K = 2 * M, nm = pl.nmodes;
     // geometry list in storage order: level, station, slot (only the finest
-    // level when the levels share its tables: square on the axis)
+    // level when the levels share its tables: square on the axis); the plan
+    // keeps it until the copy has run
     std::vector<GeomDesc> geoms;
     for (int l = pl.rlo == 0.0 ? pl.d : 2; l <= pl.d; ++l) {
         int nb = 1 << l;
@@ -431,7 +433,10 @@ void build_tables(Plan &pl, hipStream_t st)
     // scratch (plan arena): geometry descriptors and starting columns
     GeomDesc *dgeo = reinterpret_cast<GeomDesc *>(pl.tab_scratch);
     double *dstart = reinterpret_cast<double *>(pl.tab_scratch) + 4 * (size_t)ng;
-    AXF_HIP(hipMemcpyAsync(dgeo, geoms.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
+    static_assert(sizeof(GeomDesc) == 4 * sizeof(double), "geometry record");
+    pl.geom_host.resize(4 * (size_t)ng);
+    std::memcpy(pl.geom_host.data(), geoms.data(), sizeof(GeomDesc) * ng);
+    AXF_HIP(hipMemcpyAsync(dgeo, pl.geom_host.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
     size_t sm_start = start_lds_bytes(M, nm);
     static bool attr_done[64] = {};
     if (!attr_done[pl.device & 63]) {
@@ -444,8 +449,6 @@ void build_tables(Plan &pl, hipStream_t st)
     double *tab = pl.lev[2].tab;
     k_tab_laplace<<<ng * nm, kLapThreads, 0, st>>>(M, nm, dgeo, dstart, tab);
     AXF_HIP(hipGetLastError());
-    // the host geometry list must outlive the copy
-    AXF_HIP(hipStreamSynchronize(st));
     (void)TS;
 }
 

@@ -425,7 +425,7 @@ struct PointScratch {
 }  // namespace
 
 void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, const double *zf,
-                hipStream_t st)
+                hipStream_t st, const std::function<void()> &after_depth)
 {
     const int64_t ns = pl.src.n, nf = pl.fld.n;
     const int64_t nmax = std::max(ns, nf);
@@ -539,6 +539,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
         }
     }
     pl.d = d;
+    after_depth();
 
     // ---- per side: keys at depth d, sort, gather coordinates
     const int bits = 2 * d;
