@@ -340,6 +340,7 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
 {
     __shared__ double col[2][AXF_MAX_ORDER + 1][2 * AXF_MAX_ORDER + 1];   // rows (a, b) for b = 0, 1
     __shared__ double fact[2 * AXF_MAX_ORDER + 2];
+    __shared__ double rstep[AXF_MAX_ORDER + 1];    // 1 / ((i + 1)(i + 2))
     const int K = 2 * M;
     const int g = blockIdx.x / nmodes, n = blockIdx.x - g * nmodes;
     const GeomDesc gd = geoms[g];
@@ -355,6 +356,9 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
             f *= (c + 1.0);
         }
     }
+    if (tid <= M) rstep[tid] = 1.0 / ((tid + 1.0) * (tid + 2.0));
+    __syncthreads();
+    const double nir2 = -1.0 / (r * r), nir12 = -1.0 / (r1 * r1);
     const double *st = start + ((size_t)g * nmodes + n) * 4 * (K + 1);
     // r recursion of column b (wave b): rows (i, b), i = 0..M, length K + 1 - i - b
     if (w < 2 && (w == 0 || M >= 1)) {
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
         for (int i = 0; i + 2 <= M; ++i) {
             const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
             const double c1 = r * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
-            const double inv = -1.0 / (r * r * (i + 1.0) * (i + 2.0));
+            const double inv = nir2 * rstep[i];
             const double gn = lap_step(c1, c0, r * r, 2.0 * r, inv, kk, g1, g0, h0, i >= 1 ? hm1 : 0.0,
                                        i >= 2 ? hm2 : 0.0);
             gm2 = gm1;
@@ -390,7 +394,7 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
         for (int j = 0; j + 2 <= M; ++j) {
             const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
             const double c1 = r1 * (j + 1.0) * (2.0 * j + 1.0), c0 = (double)j * j - n2;
-            const double inv = -1.0 / (r1 * r1 * (j + 1.0) * (j + 2.0));
+            const double inv = nir12 * rstep[j];
             const double gn = lap_step(c1, c0, r1 * r1, 2.0 * r1, inv, kk, g1, g0, h0, j >= 1 ? hm1 : 0.0,
                                        j >= 2 ? hm2 : 0.0);
             gm2 = gm1;
