@@ -8,8 +8,10 @@ relative to the largest entry of the same total order a + b + c (the scale at
 which they enter the S2L sum).  Geometries cover stations next to the axis,
 far from it (where the starting formulas lose ~14 digits in FP64 and both
 sides use extended precision), and every separation.  The geometry is that of
-the plan (the tight bounding square), so "axis" inputs put station 0 half a
-box from r = 0.
+the plan's square: for the "axis" inputs it starts on the axis (station 0
+half a box from r = 0), and then the coarser levels' tables are the finest
+level's scaled by 2^(l-d), so both the shared and the per-level storage are
+checked at every level.
 """
 import math
 
@@ -64,6 +66,8 @@ def test_tables_vs_oracle(geom, nmodes, M, depth, tol):
         r, z, _ = inputs.paper_unit(4000, 1, seed=8)
     plan = axf.Plan(r, z, r, z, nmodes, M, depth=depth)
     rlo, zlo, L, invL = O.square_info(r, z, r, z)
+    assert (rlo == 0.0) == (geom == "axis")       # shared tables only on the axis
+    assert plan.info()["square"][0] == rlo
     worst = 0.0
     for level in range(2, depth + 1):
         nb = 1 << level
