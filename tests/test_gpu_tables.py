@@ -8,10 +8,11 @@ relative to the largest entry of the same total order a + b + c (the scale at
 which they enter the S2L sum).  Geometries cover stations next to the axis,
 far from it (where the starting formulas lose ~14 digits in FP64 and both
 sides use extended precision), and every separation.  The geometry is that of
-the plan's square: for the "axis" inputs it starts on the axis (station 0
-half a box from r = 0), and then the coarser levels' tables are the finest
-level's scaled by 2^(l-d), so both the shared and the per-level storage are
-checked at every level.
+the plan's square.  For the "annulus" inputs (r extent 0.9 < z extent 2) it
+starts on the axis (station 0 half a box from r = 0) and the coarser levels'
+tables are the finest level's scaled by 2^(l-d); the "curve" and "axis"
+inputs keep one table set per level.  Both storages are checked at every
+level.
 """
 import math
 
@@ -52,7 +53,8 @@ def _order_scaled_err(got, ref, M):
 # Next to the axis (inner centre half a box from it) the FP64 Laplace recursion
 # itself carries ~1e-11 (17 modes, M = 12) of the order scale on both sides.
 CASES = [("curve", 5, 9, 3, 1e-12), ("curve", 33, 16, 6, 1e-11),
-         ("axis", 5, 9, 3, 1e-12), ("axis", 17, 12, 4, 1e-10)]
+         ("axis", 5, 9, 3, 1e-12), ("axis", 17, 12, 4, 1e-10),
+         ("annulus", 5, 9, 3, 1e-12), ("annulus", 17, 12, 4, 1e-12)]
 
 
 @gpu
@@ -62,11 +64,13 @@ def test_tables_vs_oracle(geom, nmodes, M, depth, tol):
     from paper_2301_01179_amd import axf
     if geom == "curve":
         r, z, _ = inputs.generator_curve(4000, 1, seed=3)
-    else:
+    elif geom == "axis":
         r, z, _ = inputs.paper_unit(4000, 1, seed=8)
+    else:
+        r, z, _, _, _ = inputs.annulus(4000, 10, 1, seed=5)
     plan = axf.Plan(r, z, r, z, nmodes, M, depth=depth)
     rlo, zlo, L, invL = O.square_info(r, z, r, z)
-    assert (rlo == 0.0) == (geom == "axis")       # shared tables only on the axis
+    assert (rlo == 0.0) == (geom == "annulus")    # which storage the case checks
     assert plan.info()["square"][0] == rlo
     worst = 0.0
     for level in range(2, depth + 1):
