@@ -168,7 +168,7 @@ __host__ __device__ void green_dd(int N, double r, double r1, double x, double c
 // three-term recurrence that multiplying by rho^2(x + t) gives.
 __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, double chistar,
                                                             const GeomDesc *__restrict__ geoms,
-                                                            double *__restrict__ out)
+                                                            dd *__restrict__ hand)
 {
     extern __shared__ dd smd[];
     const int K = 2 * M;
@@ -177,8 +177,7 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
     dd *up = smd, *um = up + L, *fp = um + L, *fm = fp + L, *pp = fm + L, *pm = pp + L, *qp = pm + L,
        *qm = qp + L, *dp = qm + L, *dm = dp + L;
     dd *g00 = dm + L;                 // [Nw+1][L]
-    dd *g01 = g00 + (Nw + 1) * L;     // [Nw+1][L]
-    dd *rinv = g01 + (Nw + 1) * L;    // 1 / (k + 1), k < L
+    dd *rinv = g00 + (Nw + 1) * L;    // 1 / (k + 1), k < L
     const GeomDesc gd = geoms[blockIdx.x];
     const double r = gd.rout, r1 = gd.rin, x = gd.x;
     const int tid = threadIdx.x;
@@ -186,7 +185,6 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
     const int n = tid / lpm, j = tid - n * lpm;      // mode and lane within the mode
     const bool active = n <= Nw;
     const int nm = n == 0 ? 1 : n - 1;
-    double *o = out + (size_t)blockIdx.x * nmodes * 4 * L;
     if (tid == 0) green_dd(Nw, r, r1, x, chistar, g00, L);
     if (tid == 64 || (tid == 0 && blockDim.x <= 64)) {
         for (int sgn = 0; sgn < 2; ++sgn) {
@@ -253,57 +251,112 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
         }
         __syncthreads();
     }
-    // r-derivative and its r <-> r1 image: g10 goes out, g01 stays for g11.
-    // Every (mode, k) entry is an independent sum of k + 1 terms; a thread
-    // takes the entries k and n - 1 - k of one mode (n entries per mode), so
-    // every thread sums n + 1 terms and a wave's lanes finish together.
+    // hand the x column of every mode and the rational series to the
+    // r-derivative kernel: [g00: Nw+1][fp fm pp pm qp qm dp dm][L]
+    __syncthreads();
+    dd *h = hand + (size_t)blockIdx.x * (Nw + 9) * L;
+    for (int e = tid; e < (Nw + 1) * L; e += blockDim.x) h[e] = g00[e];
+    for (int e = tid; e < 8 * L; e += blockDim.x) h[(Nw + 1) * L + e] = fp[e];   // fp..dm are contiguous
+}
+
+// Modes per block of the r-derivative kernel and its threads.
+constexpr int kStartModes = 8;
+constexpr int kStartRThreads = 256;
+
+// The r- and r1-derivative columns g_{1,0,k}, g_{0,1,k} and the mixed g_{1,1,k}
+// of kStartModes modes of one geometry (App. A, first-derivative starting
+// formulas), from the x columns and series of k_tab_start; writes the
+// starting columns [geom][n][4][2M+1] of the Laplace recursion.  Every
+// (mode, k) entry is an independent sum of k + 1 terms; a thread takes the
+// entries k and K - 1 - k of one mode, so every thread sums the same count.
+// g_{0,1} of mode m0 - 1 (and of mode 1 for mode 0, g^(-1) = g^(1)) is
+// recomputed here for the mixed column.
+__global__ __launch_bounds__(kStartRThreads) void k_tab_start_r(int M, int nmodes, const GeomDesc *__restrict__ geoms,
+                                                               const dd *__restrict__ hand,
+                                                               double *__restrict__ out)
+{
+    extern __shared__ dd smr[];
+    const int K = 2 * M, L = K + 1;
+    const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;
+    const int ngr = (nmodes + kStartModes - 1) / kStartModes;
+    const int g = blockIdx.x / ngr, grp = blockIdx.x - g * ngr;
+    const int m0 = grp * kStartModes, m1 = min(m0 + kStartModes, nmodes);
+    // modes whose g01 is needed: [lo, hi)
+    const int lo = m0 == 0 ? 0 : m0 - 1, hi = m0 == 0 ? max(m1, 2) : m1;
+    const int nw = hi - lo;
+    const GeomDesc gd = geoms[g];
+    const double r = gd.rout, r1 = gd.rin;
+    const int tid = threadIdx.x;
+    dd *g00 = smr;                               // [Nw+1][L]
+    dd *fp = g00 + (Nw + 1) * L, *fm = fp + L, *pp = fm + L, *pm = pp + L, *qp = pm + L, *qm = qp + L,
+       *dp = qm + L, *dm = dp + L;
+    dd *S = dm + L, *D = S + nw * L;             // g00[m] +- g00[mm], m in [lo, hi)
+    dd *g01 = D + nw * L;                        // [lo, hi)
+    dd *S1 = g01 + nw * L, *D1 = S1 + nw * L;    // g01[m] +- g01[mm]
+    const dd *h = hand + (size_t)g * (Nw + 9) * L;
+    for (int e = tid; e < (Nw + 9) * L; e += blockDim.x) g00[e] = h[e];
+    __syncthreads();
+    for (int e = tid; e < nw * L; e += blockDim.x) {
+        const int m = lo + e / L, k = e - (e / L) * L;
+        const int mm = m == 0 ? 1 : m - 1;
+        S[e] = g00[m * L + k] + g00[mm * L + k];
+        D[e] = g00[m * L + k] - g00[mm * L + k];
+    }
+    __syncthreads();
+    double *o = out + (size_t)g * nmodes * 4 * L;
     if (M >= 1) {
+        const dd i2r = dd_d(1.0) / dd_d(2.0 * r), i2r1 = dd_d(1.0) / dd_d(2.0 * r1);
         auto g10_entry = [&](int m, int k) {
-            const int mm = m == 0 ? 1 : m - 1;
+            const dd *Sm = S + (m - lo) * L, *Dm = D + (m - lo) * L;
             dd s1 = dd_d(0.0), s2 = dd_d(0.0);
             for (int q = 0; q <= k; ++q) {
-                const dd a = g00[m * L + k - q], b = g00[mm * L + k - q];
-                const dd sp = a + b, sm = a - b;
+                const dd sp = Sm[k - q], sm = Dm[k - q];
                 s1 = s1 + sp * pp[q] + sm * pm[q];
                 s2 = s2 + sp * qp[q] + sm * qm[q];
             }
-            const dd g = g00[m * L + k];
-            g01[m * L + k] = (s2 * (m - 0.5) - g) / dd_d(2.0 * r1);
-            if (m < nmodes) o[((size_t)m * 4 + 1) * L + k] = ((s1 * (m - 0.5) - g) / dd_d(2.0 * r)).hi;
+            const dd gg = g00[m * L + k];
+            g01[(m - lo) * L + k] = (s2 * (m - 0.5) - gg) * i2r1;
+            if (m >= m0 && m < m1) o[((size_t)m * 4 + 1) * L + k] = ((s1 * (m - 0.5) - gg) * i2r).hi;
         };
         const int h10 = (K + 1) / 2;
-        for (int e = tid; e < (Nw + 1) * h10; e += blockDim.x) {
-            const int m = e / h10, k = e - m * h10;
+        for (int e = tid; e < nw * h10; e += blockDim.x) {
+            const int m = lo + e / h10, k = e - (e / h10) * h10;
             g10_entry(m, k);
             if (K - 1 - k != k) g10_entry(m, K - 1 - k);
         }
         __syncthreads();
-        auto g11_entry = [&](int m, int k) {
+        for (int e = tid; e < (m1 - m0) * (K - 1); e += blockDim.x) {
+            const int m = m0 + e / (K - 1), k = e - (e / (K - 1)) * (K - 1);
             const int mm = m == 0 ? 1 : m - 1;
+            S1[(m - lo) * L + k] = g01[(m - lo) * L + k] + g01[(mm - lo) * L + k];
+            D1[(m - lo) * L + k] = g01[(m - lo) * L + k] - g01[(mm - lo) * L + k];
+        }
+        __syncthreads();
+        auto g11_entry = [&](int m, int k) {
+            const dd *Sm = S + (m - lo) * L, *Dm = D + (m - lo) * L;
+            const dd *S1m = S1 + (m - lo) * L, *D1m = D1 + (m - lo) * L;
             dd s = dd_d(0.0);
-            for (int q = 0; q <= k; ++q) {
-                const dd a = g00[m * L + k - q], b = g00[mm * L + k - q];
-                const dd e1 = g01[m * L + k - q], f1 = g01[mm * L + k - q];
-                s = s + (a + b) * dp[q] + (e1 + f1) * pp[q] + (a - b) * dm[q] + (e1 - f1) * pm[q];
-            }
-            o[((size_t)m * 4 + 3) * L + k] = ((s * (m - 0.5) - g01[m * L + k]) / dd_d(2.0 * r)).hi;
+            for (int q = 0; q <= k; ++q)
+                s = s + Sm[k - q] * dp[q] + S1m[k - q] * pp[q] + Dm[k - q] * dm[q] + D1m[k - q] * pm[q];
+            o[((size_t)m * 4 + 3) * L + k] = ((s * (m - 0.5) - g01[(m - lo) * L + k]) * i2r).hi;
         };
         const int h11 = K / 2;   // K - 1 entries per mode, paired
-        for (int e = tid; e < nmodes * h11; e += blockDim.x) {
-            const int m = e / h11, k = e - m * h11;
+        for (int e = tid; e < (m1 - m0) * h11; e += blockDim.x) {
+            const int m = m0 + e / h11, k = e - (e / h11) * h11;
             g11_entry(m, k);
             if (K - 2 - k != k) g11_entry(m, K - 2 - k);
         }
     }
-    // g00, g01 and the zero tails
-    for (int e = tid; e < nmodes * 4 * L; e += blockDim.x) {
-        int nn = e / (4 * L), rem = e - nn * 4 * L, col = rem / L, k = rem - col * L;
+    // g00, g01 and the zero tails of this block's modes
+    for (int e = tid; e < (m1 - m0) * 4 * L; e += blockDim.x) {
+        const int nn = m0 + e / (4 * L), rem = e - (e / (4 * L)) * 4 * L, col = rem / L, k = rem - col * L;
+        const size_t oe = ((size_t)nn * 4 + col) * L + k;
         if (col == 0) {
-            o[e] = g00[nn * L + k].hi;
+            o[oe] = g00[nn * L + k].hi;
         } else if (col == 2) {
-            o[e] = (M >= 1 && k <= K - 1) ? g01[nn * L + k].hi : 0.0;
+            o[oe] = (M >= 1 && k <= K - 1) ? g01[(nn - lo) * L + k].hi : 0.0;
         } else if (M < 1 || (col == 1 && k > K - 1) || (col == 3 && k > K - 2)) {
-            o[e] = 0.0;
+            o[oe] = 0.0;
         }
     }
 }
@@ -311,7 +364,14 @@ __global__ __launch_bounds__(kStartThreads) void k_tab_start(int M, int nmodes, 
 size_t start_lds_bytes(int M, int nmodes)
 {
     const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;
-    return sizeof(dd) * (size_t)(2 * M + 1) * (11 + 2 * (Nw + 1));
+    return sizeof(dd) * (size_t)(2 * M + 1) * (11 + (Nw + 1));
+}
+
+size_t start_r_lds_bytes(int M, int nmodes)
+{
+    const int Nw = nmodes - 1 < 1 ? 1 : nmodes - 1;
+    const int nw = kStartModes + 1;   // the group's modes and one below (or mode 1)
+    return sizeof(dd) * (size_t)(2 * M + 1) * ((Nw + 1) + 8 + 5 * nw);
 }
 
 // Laplace recursion for one (geometry, mode); writes the scaled table.
@@ -441,14 +501,19 @@ void build_tables(Plan &pl, hipStream_t st)
     pl.geom_host.resize(4 * (size_t)ng);
     std::memcpy(pl.geom_host.data(), geoms.data(), sizeof(GeomDesc) * ng);
     AXF_HIP(hipMemcpyAsync(dgeo, pl.geom_host.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
-    size_t sm_start = start_lds_bytes(M, nm);
+    // x columns and series of each geometry, handed to the r-derivative kernel
+    dd *hand = reinterpret_cast<dd *>(dstart + (size_t)ng * nm * 4 * (K + 1));
     static bool attr_done[64] = {};
     if (!attr_done[pl.device & 63]) {
         AXF_HIP(hipFuncSetAttribute((const void *)k_tab_start, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)start_lds_bytes(AXF_MAX_ORDER, AXF_MAX_MODES)));
+        AXF_HIP(hipFuncSetAttribute((const void *)k_tab_start_r, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)start_r_lds_bytes(AXF_MAX_ORDER, AXF_MAX_MODES)));
         attr_done[pl.device & 63] = true;
     }
-    k_tab_start<<<ng, kStartThreads, sm_start, st>>>(M, nm, pl.chistar, dgeo, dstart);
+    k_tab_start<<<ng, kStartThreads, start_lds_bytes(M, nm), st>>>(M, nm, pl.chistar, dgeo, hand);
+    const int ngr = (nm + kStartModes - 1) / kStartModes;
+    k_tab_start_r<<<ng * ngr, kStartRThreads, start_r_lds_bytes(M, nm), st>>>(M, nm, dgeo, hand, dstart);
     // tables of level l start at geometry index 12 * (2^l - 4)
     double *tab = pl.lev[2].tab;
     k_tab_laplace<<<ng * nm, kLapThreads, 0, st>>>(M, nm, dgeo, dstart, tab);
@@ -458,8 +523,11 @@ void build_tables(Plan &pl, hipStream_t st)
 
 size_t table_scratch_doubles(int d, int M, int nmodes)
 {
-    size_t ng = 12 * (((size_t)1 << (d + 1)) - 4);
-    return 4 * ng + ng * (size_t)nmodes * 4 * (2 * M + 1);
+    const size_t ng = 12 * (((size_t)1 << (d + 1)) - 4);
+    const size_t L = 2 * (size_t)M + 1;
+    const size_t nw1 = nmodes < 2 ? 2 : nmodes;   // modes 0..Nw of the x columns
+    // geometries, starting columns, and the x columns + series in double-double
+    return 4 * ng + ng * (size_t)nmodes * 4 * L + ng * 2 * (nw1 + 8) * L;
 }
 
 }  // namespace axf
