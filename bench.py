@@ -219,8 +219,8 @@ def measure_batch(torch, axf, inputs, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a run over "
+              "several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 
