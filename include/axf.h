@@ -53,7 +53,7 @@ typedef enum {
     AXF_ERR_HIP = 5                /* a HIP runtime call failed                */
 } axf_status;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define AXF_MAX_MODES 64   /* n_modes = N + 1 <= 64                     */
 #define AXF_MAX_ORDER 24   /* expansion order M <= 24                   */
 #define AXF_MAX_DEPTH 11   /* tree depth d <= 11                        */
