@@ -382,16 +382,74 @@ size_t start_r_lds_bytes(int M, int nmodes)
 //   r^2 (i+1)(i+2) g_(i+2) = -[ r (i+1)(2i+1) g_(i+1) + (i^2 - n^2) g_i
 //                               + r^2 h_i + 2 r h_(i-1) + h_(i-2) ],
 //   h_m = (k+1)(k+2) g_(m, k+2);  and the same in r1 for the source index.
-// One wave runs one recursion with lane k holding the x index k of the last
-// four rows; the k + 2 entries come from lane k + 2 by a shuffle.  Waves 0
-// and 1 run the r recursion of the columns b = 0 and 1 (rows staged in LDS),
-// then the four waves share the r1 recursions, one per a.
+// Each 16-lane row of a wave runs one recursion; lane l of the row holds the
+// x indices k = l + 16t, t = 0..3, of the last four rows (a row's stores are
+// contiguous), so the k + 2 entry is lane l + 2's element t, or for l >= 14
+// lane l - 14's element t + 1: one DPP rotation of the row by two lanes.
+// Two rows run the r recursions of the columns b = 0 and 1 (rows staged in
+// LDS), then the 16 rows of the block share the r1 recursions, one per a.
 constexpr int kLapThreads = 256;
+constexpr int kLapRecs = kLapThreads / 16;      // recursions in flight per block
 __device__ __forceinline__ double lap_step(double c1, double c0, double s2, double s1, double inv, double kk,
                                            double g1, double g0, double h0, double hm1, double hm2)
 {
     // -(c1 g_(i+1) + c0 g_i + kk (s2 h_i + s1 h_(i-1) + h_(i-2))) / (s2 (i+1)(i+2)), inv = -1/(...)
     return (c1 * g1 + c0 * g0 + kk * (s2 * h0 + s1 * hm1 + hm2)) * inv;
+}
+
+// The value of lane (l + 2) mod 16 of the 16-lane row (DPP row_ror:14).
+__device__ __forceinline__ double row_plus2(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x12e, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x12e, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The k + 2 entries of the lane's four x indices for one row of values.
+__device__ __forceinline__ void plus2(const double (&v)[4], int l16, double (&h)[4])
+{
+    double rot[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) rot[t] = row_plus2(v[t]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h[t] = l16 < 14 ? rot[t] : (t < 3 ? rot[t + 1] : 0.0);
+}
+
+// One recursion over rows i = 0..M of a column of length K + 1 - base - i
+// (base = b for the r recursion, a for the r1 one): rows 0 and 1 given, the
+// rest from the Laplace step with coefficient scale rr (r or r1); each new
+// row is passed to emit(i, t, value) for its valid entries.
+template <class Emit>
+__device__ __forceinline__ void lap_run(int M, int K, int base, double rr, double nirr, double n2,
+                                        const double *rstep, double (&g0)[4], double (&g1)[4], int l16,
+                                        Emit emit)
+{
+    double gm1[4] = {0.0, 0.0, 0.0, 0.0}, gm2[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i + 2 <= M; ++i) {
+        const double c1 = rr * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
+        const double inv = nirr * rstep[i];
+        double h0[4], hm1[4], hm2[4], gn[4];
+        plus2(g0, l16, h0);
+        plus2(gm1, l16, hm1);
+        plus2(gm2, l16, hm2);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = l16 + 16 * t;
+            const double kk = (k + 1.0) * (k + 2.0);
+            gn[t] = lap_step(c1, c0, rr * rr, 2.0 * rr, inv, kk, g1[t], g0[t], h0[t], i >= 1 ? hm1[t] : 0.0,
+                             i >= 2 ? hm2[t] : 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = l16 + 16 * t;
+            const bool valid = k <= K - base - (i + 2);
+            gm2[t] = gm1[t];
+            gm1[t] = g0[t];
+            g0[t] = g1[t];
+            g1[t] = valid ? gn[t] : 0.0;
+            if (valid) emit(i + 2, t, g1[t]);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, const GeomDesc *__restrict__ geoms,
@@ -406,8 +464,7 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
     const GeomDesc gd = geoms[g];
     const double r = gd.rout, r1 = gd.rin;
     const double n2 = (double)n * n;
-    const int tid = threadIdx.x, w = tid >> 6, k = tid & 63;
-    const double kk = (k + 1.0) * (k + 2.0);
+    const int tid = threadIdx.x, rec = tid >> 4, l16 = tid & 15;
     double *out = tab + ((size_t)g * nmodes + n) * (size_t)((M + 1) * (M + 1) * (M + 1));
     if (tid == 0) {
         double f = 1.0;
@@ -420,50 +477,37 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
     __syncthreads();
     const double nir2 = -1.0 / (r * r), nir12 = -1.0 / (r1 * r1);
     const double *st = start + ((size_t)g * nmodes + n) * 4 * (K + 1);
-    // r recursion of column b (wave b): rows (i, b), i = 0..M, length K + 1 - i - b
-    if (w < 2 && (w == 0 || M >= 1)) {
-        const int bcol = w;
-        const int len0 = K + 1 - bcol;
-        double gm2 = 0.0, gm1 = 0.0;                           // rows i-2, i-1
-        double g0 = k < len0 ? st[(bcol == 0 ? 0 : 2) * (K + 1) + k] : 0.0;          // row 0
-        double g1 = (M >= 1 && k < len0 - 1) ? st[(bcol == 0 ? 1 : 3) * (K + 1) + k] : 0.0;   // row 1
-        if (k < len0) col[bcol][0][k] = g0;
-        if (M >= 1 && k < len0 - 1) col[bcol][1][k] = g1;
-        for (int i = 0; i + 2 <= M; ++i) {
-            const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
-            const double c1 = r * (i + 1.0) * (2.0 * i + 1.0), c0 = (double)i * i - n2;
-            const double inv = nir2 * rstep[i];
-            const double gn = lap_step(c1, c0, r * r, 2.0 * r, inv, kk, g1, g0, h0, i >= 1 ? hm1 : 0.0,
-                                       i >= 2 ? hm2 : 0.0);
-            gm2 = gm1;
-            gm1 = g0;
-            g0 = g1;
-            g1 = k <= K - (i + 2) - bcol ? gn : 0.0;
-            if (k <= K - (i + 2) - bcol) col[bcol][i + 2][k] = g1;
+    // r recursion of column b (rows 0 and 1 of wave 0): rows (i, b), i = 0..M,
+    // length K + 1 - i - b, staged in LDS
+    if (rec < 2 && (rec == 0 || M >= 1)) {
+        const int bcol = rec, len0 = K + 1 - bcol;
+        double g0[4], g1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = l16 + 16 * t;
+            g0[t] = k < len0 ? st[(bcol == 0 ? 0 : 2) * (K + 1) + k] : 0.0;
+            g1[t] = (M >= 1 && k < len0 - 1) ? st[(bcol == 0 ? 1 : 3) * (K + 1) + k] : 0.0;
+            if (k < len0) col[bcol][0][k] = g0[t];
+            if (M >= 1 && k < len0 - 1) col[bcol][1][k] = g1[t];
         }
+        lap_run(M, K, bcol, r, nir2, n2, rstep, g0, g1, l16,
+                [&](int i, int t, double v) { col[bcol][i][l16 + 16 * t] = v; });
     }
     __syncthreads();
     // r1 recursion for each a: rows (a, j), j = 0..M, length K + 1 - a - j
-    for (int a = w; a <= M; a += kLapThreads / 64) {
-        double gm2 = 0.0, gm1 = 0.0;
-        double g0 = k <= K - a ? col[0][a][k] : 0.0;
-        double g1 = (M >= 1 && k <= K - a - 1) ? col[1][a][k] : 0.0;
-        const double fk = k <= K ? fact[k] * gd.invh : 0.0;
-        if (k <= K - a) out[table_row(M, a, 0) + k] = g0 * fk;
-        if (M >= 1 && k <= K - a - 1) out[table_row(M, a, 1) + k] = g1 * fk;
-        for (int j = 0; j + 2 <= M; ++j) {
-            const double h0 = __shfl_down(g0, 2, 64), hm1 = __shfl_down(gm1, 2, 64), hm2 = __shfl_down(gm2, 2, 64);
-            const double c1 = r1 * (j + 1.0) * (2.0 * j + 1.0), c0 = (double)j * j - n2;
-            const double inv = nir12 * rstep[j];
-            const double gn = lap_step(c1, c0, r1 * r1, 2.0 * r1, inv, kk, g1, g0, h0, j >= 1 ? hm1 : 0.0,
-                                       j >= 2 ? hm2 : 0.0);
-            gm2 = gm1;
-            gm1 = g0;
-            g0 = g1;
-            const bool valid = k <= K - a - (j + 2);
-            g1 = valid ? gn : 0.0;
-            if (valid) out[table_row(M, a, j + 2) + k] = g1 * fk;
+    for (int a = rec; a <= M; a += kLapRecs) {
+        double g0[4], g1[4], fk[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = l16 + 16 * t;
+            g0[t] = k <= K - a ? col[0][a][k] : 0.0;
+            g1[t] = (M >= 1 && k <= K - a - 1) ? col[1][a][k] : 0.0;
+            fk[t] = k <= K ? fact[k] * gd.invh : 0.0;
+            if (k <= K - a) out[table_row(M, a, 0) + k] = g0[t] * fk[t];
+            if (M >= 1 && k <= K - a - 1) out[table_row(M, a, 1) + k] = g1[t] * fk[t];
         }
+        lap_run(M, K, a, r1, nir12, n2, rstep, g0, g1, l16,
+                [&](int j, int t, double v) { out[table_row(M, a, j) + l16 + 16 * t] = v * fk[t]; });
     }
 }
 
