@@ -88,7 +88,10 @@ typedef struct axf_plan axf_plan;   /* opaque; owned by the library */
  *   r_fld, z_fld : [nf] field points (device).  May alias the sources.
  * The plan copies what it needs; the coordinate buffers may be freed after
  * the call returns.  This call synchronises `stream` (it reads back the
- * bounding square and the tree occupancy) and allocates device memory.
+ * bounding square and the tree occupancy) and allocates device memory.  The
+ * tables are built on an internal stream of the library and may still be in
+ * flight when the call returns: every later call that reads them waits for
+ * them on its own stream (evaluations just before their first S2L pass).
  * Returns AXF_ERR_INVALID_GEOMETRY if any r <= 0 or any coordinate is not
  * finite; ns >= 1 and nf >= 1 are required. */
 axf_status axf_plan_create(const axf_params *params,

@@ -124,6 +124,8 @@ void plan_release(Plan *pl)
     if (!pl) return;
     (void)hipDeviceSynchronize();
     release_events(pl);
+    if (pl->tables_ready) (void)hipEventDestroy(pl->tables_ready);
+    pl->tables_ready = nullptr;
     arena_release(pl->points);
     arena_release(pl->tree);
     arena_release(pl->expn);
@@ -201,6 +203,8 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         AXF_HIP(hipStreamWaitEvent(side, ev, 0));
         pl.spare_events.push_back(ev);   // reusable: the wait has been enqueued
         build_tables(pl, side);
+        if (!pl.tables_ready) AXF_HIP(hipEventCreateWithFlags(&pl.tables_ready, hipEventDisableTiming));
+        AXF_HIP(hipEventRecord(pl.tables_ready, side));
     };
     build_tree(pl, rs, zs, rf, zf, st, start_tables);
     build_tiles(pl, st);
@@ -232,10 +236,9 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
     pl.s2l_part = pl.expn.take<double2>(std::max<size_t>(part, 1));
-    // join: the tables are complete before the plan is used on any stream
-    AXF_HIP(hipStreamSynchronize(side));
-    pl.geom_host.clear();
-    pl.geom_host.shrink_to_fit();
+    // The tables may still be running on the table stream: the evaluation
+    // passes wait for `tables_ready` on their own stream just before the
+    // first S2L, so the gather, P2M and M2M overlap them.
     pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes + pl.tabmem.bytes;
 }
 

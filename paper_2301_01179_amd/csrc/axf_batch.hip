@@ -227,6 +227,9 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             b->depth.push_back(pl->d);
             maxd = std::max(maxd, pl->d);
         }
+        // the batch's passes do not wait on the table stream: tables first
+        for (Plan *pl : b->plans)
+            if (pl->tables_ready) AXF_HIP(hipEventSynchronize(pl->tables_ready));
         // descriptors and merged queues
         std::vector<ProbDev> pd(nprob);
         std::vector<int2> qg, qp, ql;

@@ -1348,6 +1348,8 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
                                                    pl.lev[l].mom);
     }
     {
+        // the tables (built on the table stream) are needed from here on
+        if (pl.tables_ready) AXF_HIP(hipStreamWaitEvent(st, pl.tables_ready, 0));
         for (int l = 2; l <= d; ++l) {
             if (tgt.ntiles[l] == 0) continue;
             launch_s2l(pl, src, tgt, l, st);

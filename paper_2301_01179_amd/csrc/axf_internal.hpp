@@ -164,7 +164,8 @@ struct Plan {
     double *gsum = nullptr;     // adjoint coordinate-gradient scratch
     double *tab_scratch = nullptr;
     Arena points, tree, expn, tilemem, tabmem;
-    std::vector<double> geom_host;   // table geometries (4 doubles each) until the tables are built
+    std::vector<double> geom_host;   // table geometries (4 doubles each), source of an async copy
+    hipEvent_t tables_ready = nullptr;   // recorded after the tables on the table stream
     int64_t near_pairs = 0, s2l_pairs = 0, s2l_units = 0;   // S2L: box pairs, (box, offset unit) pairs
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
