@@ -227,6 +227,7 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
                 part = std::max(part, (size_t)sd->s2l_groups[l] * sd->nocc[l] * pl.C * pl.P);
         }
     sz.add<double2>(std::max<size_t>(part, 1));
+    sz.add<double>((size_t)6 * kCoefS * kCoefS);
     pl.expn = arena_acquire(sz.bytes + 4096);
     for (int l = 2; l <= d; ++l) {
         size_t nb = (size_t)std::max(pl.src.nocc[l], pl.fld.nocc[l]);
@@ -236,6 +237,11 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         pl.lev[l].loc = pl.expn.take<double2>(std::max<size_t>(nb, 1) * pl.C * pl.P);
     }
     pl.s2l_part = pl.expn.take<double2>(std::max<size_t>(part, 1));
+    // M2M and L2L shift factors (the host copy lives with the plan)
+    pl.shift_coef = pl.expn.take<double>((size_t)6 * kCoefS * kCoefS);
+    shift_coef_host(pl.M, pl.coef_host);
+    AXF_HIP(hipMemcpyAsync(pl.shift_coef, pl.coef_host.data(), sizeof(double) * pl.coef_host.size(),
+                           hipMemcpyHostToDevice, st));
     // The tables may still be running on the table stream: the evaluation
     // passes wait for `tables_ready` on their own stream just before the
     // first S2L, so the gather, P2M and M2M overlap them.

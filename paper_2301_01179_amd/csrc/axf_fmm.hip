@@ -134,7 +134,7 @@ __device__ __forceinline__ void tri_decode(int M, int p, int &i, int &j)
 // (parent box, channel); the children's moments are staged in LDS.
 __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t *__restrict__ pboxes,
                                          const int32_t *__restrict__ cslot, const double2 *__restrict__ cmom,
-                                         double2 *__restrict__ pmom, int item)
+                                         double2 *__restrict__ pmom, const double *__restrict__ coef, int item)
 {
     constexpr int PM = (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 2) / 2;
     __shared__ double cfr[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
@@ -147,23 +147,10 @@ __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t 
     const int nb = 1 << level;
     const int ir = b / nb, iz = b - ir * nb;
     for (int e = threadIdx.x; e < 2 * (M + 1) * (M + 1); e += blockDim.x) {
-        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
-        int i = rem / (M + 1), a = rem - i * (M + 1);
-        double d = sg ? 0.25 : -0.25;
-        double vr = 0.0, vz = 0.0;
-        if (a <= i) {
-            double bin = 1.0, pw = 1.0, fct = 1.0;
-            for (int q = 0; q < a; ++q) bin = bin * (i - q) / (q + 1.0);
-            for (int q = 0; q < i - a; ++q) {
-                pw *= d;
-                fct *= (q + 1.0);
-            }
-            double two = ldexp(1.0, -a);
-            vr = bin * pw * two;
-            vz = pw / fct * two;
-        }
-        cfr[sg][i][a] = vr;
-        cfz[sg][i][a] = vz;
+        const int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
+        const int i = rem / (M + 1), a = rem - i * (M + 1);
+        cfr[sg][i][a] = coef[(size_t)(2 + sg) * kCoefS * kCoefS + i * kCoefS + a];
+        cfz[sg][i][a] = coef[(size_t)(4 + sg) * kCoefS * kCoefS + i * kCoefS + a];
     }
     const int cnb = nb * 2;
     for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
@@ -213,9 +200,10 @@ __device__ __forceinline__ void m2m_body(int M, int C, int level, const int32_t 
 
 __global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int32_t *__restrict__ pboxes,
                                             const int32_t *__restrict__ cslot,
-                                            const double2 *__restrict__ cmom, double2 *__restrict__ pmom)
+                                            const double2 *__restrict__ cmom, double2 *__restrict__ pmom,
+                                            const double *__restrict__ coef)
 {
-    m2m_body(M, C, level, pboxes, cslot, cmom, pmom, blockIdx.x);
+    m2m_body(M, C, level, pboxes, cslot, cmom, pmom, coef, blockIdx.x);
 }
 
 // ------------------------------------------------------------------- L2L
@@ -228,7 +216,7 @@ __global__ __launch_bounds__(256) void k_m2m(int M, int C, int level, const int3
 // S2L pass of the same level then accumulates into.
 __device__ __forceinline__ void l2l_body(int M, int C, int level, const int32_t *__restrict__ tbox,
                                          const int32_t *__restrict__ tslot_parent, const double2 *__restrict__ ploc,
-                                         double2 *__restrict__ loc, int item)
+                                         double2 *__restrict__ loc, const double *__restrict__ coef, int item)
 {
     constexpr int PM = (AXF_MAX_ORDER + 1) * (AXF_MAX_ORDER + 2) / 2;
     __shared__ double fc[2][AXF_MAX_ORDER + 1][AXF_MAX_ORDER + 1];
@@ -246,18 +234,9 @@ __device__ __forceinline__ void l2l_body(int M, int C, int level, const int32_t 
         return;
     }
     for (int e = threadIdx.x; e < 2 * (M + 1) * (M + 1); e += blockDim.x) {
-        int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
-        int i = rem / (M + 1), q = rem - i * (M + 1);
-        double d = sg ? 0.25 : -0.25, v = 0.0;
-        if (i + q <= M) {
-            double bin = 1.0, pw = 1.0;
-            for (int s = 0; s < q; ++s) {
-                bin = bin * (i + q - s) / (s + 1.0);
-                pw *= d;
-            }
-            v = bin * pw * ldexp(1.0, -i);
-        }
-        fc[sg][i][q] = v;
+        const int sg = e / ((M + 1) * (M + 1)), rem = e - sg * (M + 1) * (M + 1);
+        const int i = rem / (M + 1), q = rem - i * (M + 1);
+        fc[sg][i][q] = coef[(size_t)sg * kCoefS * kCoefS + i * kCoefS + q];
     }
     const double2 *src = ploc + ((int64_t)pslot * C + c) * P;
     for (int p = threadIdx.x; p < P; p += blockDim.x) pl[p] = src[p];
@@ -296,9 +275,10 @@ __device__ __forceinline__ void l2l_body(int M, int C, int level, const int32_t 
 
 __global__ __launch_bounds__(256) void k_l2l(int M, int C, int level, const int32_t *__restrict__ tbox,
                                             const int32_t *__restrict__ tslot_parent,
-                                            const double2 *__restrict__ ploc, double2 *__restrict__ loc)
+                                            const double2 *__restrict__ ploc, double2 *__restrict__ loc,
+                                            const double *__restrict__ coef)
 {
-    l2l_body(M, C, level, tbox, tslot_parent, ploc, loc, blockIdx.x);
+    l2l_body(M, C, level, tbox, tslot_parent, ploc, loc, coef, blockIdx.x);
 }
 
 // ------------------------------------------------------- S2L, tiled form
@@ -1079,7 +1059,7 @@ void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t s
         // locals of the level's target boxes: shifted parent expansion, or zero
         PhaseTimer tm(pl, st, AXF_PHASE_L2L);
         k_l2l<<<tgt.nocc[l] * pl.C, 256, 0, st>>>(pl.M, pl.C, l, tgt.box[l], l > 2 ? tgt.slot[l - 1] : nullptr,
-                                                   l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc);
+                                                   l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc, pl.shift_coef);
     }
     PhaseTimer tm(pl, st, AXF_PHASE_S2L);
 #define AXF_S2L_LAUNCH(LB, MW, FIX) launch_s2l_t<LB, 4, MW, FIX>(pl, src, tgt, l, st)
@@ -1171,7 +1151,7 @@ __global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, con
         const ProbDev &pd = P[it.x];
         const int l = pd.d - t;
         __syncthreads();
-        m2m_body(M, pd.C, l, pd.sbox[l], pd.sslot[l + 1], pd.mom[l + 1], pd.mom[l], it.y);
+        m2m_body(M, pd.C, l, pd.sbox[l], pd.sslot[l + 1], pd.mom[l + 1], pd.mom[l], pd.shift_coef, it.y);
     }
 }
 
@@ -1196,7 +1176,7 @@ __global__ __launch_bounds__(256) void kb_l2l(const ProbDev *__restrict__ P, con
         const ProbDev &pd = P[it.x];
         __syncthreads();
         l2l_body(M, pd.C, l, pd.tbox[l], l > 2 ? pd.tslot[l - 1] : nullptr, l > 2 ? pd.loc[l - 1] : nullptr,
-                 pd.loc[l], it.y);
+                 pd.loc[l], pd.shift_coef, it.y);
     }
 }
 
@@ -1324,6 +1304,42 @@ __global__ __launch_bounds__(256) void k_census_direct(int N, double chistar, Si
 
 }  // namespace
 
+// Shift factors of the M2M and L2L passes for order M, in the layout the
+// kernels read: [L2L F][M2M r][M2M z] x [d = -1/4, +1/4] x [S][S].
+//   L2L:  F[i][q] = C(i+q, q) d^q 2^-i,  i + q <= M;
+//   M2M:  r factor C(i, a) d^(i-a) 2^-a and z factor d^(i-a) / (i-a)! 2^-a,  a <= i.
+void shift_coef_host(int M, std::vector<double> &out)
+{
+    const int S = kCoefS;
+    out.assign((size_t)6 * S * S, 0.0);
+    for (int sg = 0; sg < 2; ++sg) {
+        const double d = sg ? 0.25 : -0.25;
+        for (int i = 0; i <= M; ++i)
+            for (int q = 0; q <= M; ++q) {
+                if (i + q <= M) {
+                    double bin = 1.0, pw = 1.0;
+                    for (int s = 0; s < q; ++s) {
+                        bin = bin * (i + q - s) / (s + 1.0);
+                        pw *= d;
+                    }
+                    out[(size_t)sg * S * S + i * S + q] = bin * pw * std::ldexp(1.0, -i);
+                }
+                const int a = q;
+                if (a <= i) {
+                    double bin = 1.0, pw = 1.0, fct = 1.0;
+                    for (int t = 0; t < a; ++t) bin = bin * (i - t) / (t + 1.0);
+                    for (int t = 0; t < i - a; ++t) {
+                        pw *= d;
+                        fct *= (t + 1.0);
+                    }
+                    const double two = std::ldexp(1.0, -a);
+                    out[(size_t)(2 + sg) * S * S + i * S + a] = bin * pw * two;
+                    out[(size_t)(4 + sg) * S * S + i * S + a] = pw / fct * two;
+                }
+            }
+    }
+}
+
 void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out, hipStream_t st)
 {
     const int M = pl.M, P = pl.P, C = pl.C, d = pl.d;
@@ -1345,7 +1361,7 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
         for (int l = d - 1; l >= 2; --l)
             if (src.nocc[l] > 0)
                 k_m2m<<<src.nocc[l] * C, 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
-                                                   pl.lev[l].mom);
+                                                   pl.lev[l].mom, pl.shift_coef);
     }
     {
         // the tables (built on the table stream) are needed from here on
@@ -1444,6 +1460,7 @@ void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd)
         pd.mom[l] = pl.lev[l].mom;
         pd.loc[l] = pl.lev[l].loc;
         pd.tab[l] = pl.lev[l].tab;
+        pd.shift_coef = pl.shift_coef;
         pd.tscale[l] = pl.lev[l].tscale;
     }
     pd.chunks = pl.fld.chunks;

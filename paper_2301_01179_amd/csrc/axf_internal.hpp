@@ -166,6 +166,8 @@ struct Plan {
     Arena points, tree, expn, tilemem, tabmem;
     std::vector<double> geom_host;   // table geometries (4 doubles each), source of an async copy
     hipEvent_t tables_ready = nullptr;   // recorded after the tables on the table stream
+    double *shift_coef = nullptr;        // M2M and L2L factors, [3][2][S][S], S = AXF_MAX_ORDER + 1
+    std::vector<double> coef_host;       // their host copy, source of an async copy
     int64_t near_pairs = 0, s2l_pairs = 0, s2l_units = 0;   // S2L: box pairs, (box, offset unit) pairs
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
@@ -201,6 +203,9 @@ void build_tiles(Plan &pl, hipStream_t st);
 // tables (axf_tables.hip)
 void build_tables(Plan &pl, hipStream_t st);
 size_t table_scratch_doubles(int d, int M, int nmodes);
+// shift factors of the M2M and L2L passes (axf_fmm.hip)
+constexpr int kCoefS = AXF_MAX_ORDER + 1;
+void shift_coef_host(int M, std::vector<double> &out);
 // FMM passes (axf_fmm.hip).  `src` carries the strengths (gathered into
 // pl.Sg), `tgt` receives the potential.  mode: 0 = potential only,
 // 1 = potential and gradient arrays, 2 = potential and the coordinate
@@ -239,6 +244,7 @@ struct ProbDev {
     const double *tab[AXF_MAX_DEPTH + 1] = {};
     double tscale[AXF_MAX_DEPTH + 1] = {};
     const int4 *chunks = nullptr;
+    const double *shift_coef = nullptr;
 };
 
 // Merged work queues of a batch: one (problem, item) list per pass.

@@ -150,3 +150,32 @@ def test_auto_depth_rule():
         if d > 2:
             assert worst(d - 1) > max_leaf
         plan.close()
+
+
+@gpu
+@pytest.mark.parametrize("order", ["created_then_other", "other_first"])
+def test_plan_on_other_stream(order):
+    """The tables of a plan are built on an internal stream and may still be
+    in flight when the plan is returned: an evaluation issued at once on a
+    different stream (default priority) waits for them before its S2L pass."""
+    need_gpu()
+    axf = _axf()
+    rs, zs, rf, zf, S = inputs.annulus(3000, 2000, 9, seed=13)
+    M, depth = 12, 4
+    s_make, s_eval = torch.cuda.Stream(), torch.cuda.Stream()
+    St = torch.from_numpy(S).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s_make):
+        plan = axf.Plan(rs, zs, rf, zf, 9, M, depth=depth)
+    if order == "other_first":
+        # queue unrelated work first so that the evaluation stream is busy
+        with torch.cuda.stream(s_eval):
+            x = torch.randn(2048, 2048, device="cuda", dtype=torch.float64)
+            for _ in range(4):
+                x = x @ x * 1e-3
+    with torch.cuda.stream(s_eval):
+        phi = plan.evaluate(St)
+    s_eval.synchronize()
+    ref = O.fmm(rs, zs, rf, zf, S, M, plan.info()["depth"])
+    assert rel_err(to_np(phi), ref).max() < TOL
+    plan.close()
