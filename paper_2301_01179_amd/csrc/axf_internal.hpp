@@ -121,8 +121,9 @@ inline int s2l_window(int M) { return M <= 4 ? 4 : (M + 3) / 4 * 4; }
 // Doubles past the last table: a lane reads its whole window, up to
 // s2l_window + 2 s2l_lb - 1 entries past the start of the table's last row.
 constexpr size_t kTablePad = 64;
-// Offset groups of a level: the 27 interaction-list offsets of a (tile,
-// channel) are split over G blocks so that a level launches ~2048 waves.
+// Offset groups of a level: the 18 offset units (pairs (dr, +-dz) of the
+// interaction list) of a (tile, channel) are split over G blocks so that a
+// level launches ~2048 waves.
 inline int s2l_group_count(int ntiles, int C, int M)
 {
     const int64_t waves = (int64_t)ntiles * C * s2l_waves(M);
