@@ -151,7 +151,9 @@ axf_status axf_plan_level_info(const axf_plan *plan, int32_t level,
  * r_in = r_lo + (station + 1/2) h, r_out = r_in + dr h and x = dz h,
  *     out[n][a][b][c] = c! * gbar^(n)_{a,b,c}(r_out, r_in, x) * h^(a+b+c)
  * for a, b <= M and a + b + c <= 2M, zero elsewhere; host array of
- * n_modes * (M+1) * (M+1) * (2M+1) doubles owned by the caller.
+ * n_modes * (M+1) * (M+1) * (2M+1) doubles owned by the caller.  Tables
+ * exist up to the station of the largest ring radius (no S2L operator reads
+ * one beyond it); other stations give AXF_ERR_INVALID_ARGUMENT.
  * Synchronous (waits for the plan's tables). */
 axf_status axf_plan_table(const axf_plan *plan, int32_t level, int32_t station, int32_t dr,
                           int32_t dz, double *host_out);

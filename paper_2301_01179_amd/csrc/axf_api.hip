@@ -404,6 +404,8 @@ axf_status axf_plan_table(const axf_plan *plan, int32_t level, int32_t station, 
         const Plan &pl = plan->pl;
         AXF_REQUIRE(level >= 2 && level <= pl.d, AXF_ERR_INVALID_ARGUMENT, "level out of range");
         AXF_REQUIRE(station >= 0 && station < (1 << level), AXF_ERR_INVALID_ARGUMENT, "station out of range");
+        AXF_REQUIRE(station <= pl.tab_smax[level], AXF_ERR_INVALID_ARGUMENT,
+                    "no table at this station: it lies beyond the largest radius");
         AXF_REQUIRE(dr >= 0 && dr <= 3 && dz >= 0 && dz <= 3 && (dr >= 2 || dz >= 2), AXF_ERR_INVALID_ARGUMENT,
                     "separation must satisfy 0 <= dr, dz <= 3, not both <= 1");
         const int M = pl.M, K = 2 * M, nm = pl.nmodes;

@@ -157,6 +157,8 @@ struct Plan {
     int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
     int nmb = 4, Cs = 4;        // mode bucket and padded channels per point in Sg
     double rlo = 0, zlo = 0, L = 1, invL = 1;
+    double rmax = 0;                     // largest ring radius of both sets
+    int tab_smax[AXF_MAX_DEPTH + 1] = {};   // last radial station with tables, per level
     double chistar = 1e300;
     Side src, fld;
     Level lev[AXF_MAX_DEPTH + 1];

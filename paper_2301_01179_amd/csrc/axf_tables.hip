@@ -27,6 +27,7 @@ namespace {
 
 struct GeomDesc {
     double rout, rin, x, invh;   // box units; invh = 1 / h
+    double slot;                 // table slot in the level-major storage
 };
 
 // ------------------------------------------------------- double-double
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
     const double r = gd.rout, r1 = gd.rin;
     const double n2 = (double)n * n;
     const int tid = threadIdx.x, rec = tid >> 4, l16 = tid & 15;
-    double *out = tab + ((size_t)g * nmodes + n) * (size_t)((M + 1) * (M + 1) * (M + 1));
+    double *out = tab + ((size_t)gd.slot * nmodes + n) * (size_t)((M + 1) * (M + 1) * (M + 1));
     if (tid == 0) {
         double f = 1.0;
         for (int c = 0; c <= K; ++c) {
@@ -516,14 +517,20 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
 void build_tables(Plan &pl, hipStream_t st)
 {
     const int M = pl.M, K = 2 * M, nm = pl.nmodes;
-    // geometry list in storage order: level, station, slot (only the finest
-    // level when the levels share its tables: square on the axis); the plan
-    // keeps it until the copy has run
+    // geometry list: level, station, separation (only the finest level when
+    // the levels share its tables: square on the axis).  A level's tables
+    // are built for the radial stations up to that of the largest radius:
+    // an S2L operator uses the table of the inner of two occupied stations,
+    // so stations beyond it are never read.  The plan keeps the list until
+    // the copy has run.
     std::vector<GeomDesc> geoms;
-    for (int l = pl.rlo == 0.0 ? pl.d : 2; l <= pl.d; ++l) {
+    const bool shared = pl.rlo == 0.0;
+    for (int l = 2; l <= pl.d; ++l) pl.tab_smax[l] = box_index(pl.rmax, pl.rlo, pl.invL, shared ? pl.d : l);
+    for (int l = shared ? pl.d : 2; l <= pl.d; ++l) {
         int nb = 1 << l;
         double h = pl.L / nb;
-        for (int s = 0; s < nb; ++s)
+        const size_t base = shared ? 0 : (size_t)12 * (((size_t)1 << l) - 4);
+        for (int s = 0; s <= pl.tab_smax[l]; ++s)
             for (int gs = 0; gs < 12; ++gs) {
                 int dr = gs < 4 ? gs / 2 : 2 + (gs - 4) / 4;
                 int dz = gs < 4 ? 2 + gs % 2 : (gs - 4) % 4;
@@ -533,6 +540,7 @@ void build_tables(Plan &pl, hipStream_t st)
                 g.rout = rin + dr;
                 g.x = dz;
                 g.invh = 1.0 / h;
+                g.slot = (double)(base + (size_t)s * 12 + gs);
                 geoms.push_back(g);
             }
     }
@@ -540,9 +548,9 @@ void build_tables(Plan &pl, hipStream_t st)
     const size_t TS = (size_t)(M + 1) * (M + 1) * (M + 1);
     // scratch (plan arena): geometry descriptors and starting columns
     GeomDesc *dgeo = reinterpret_cast<GeomDesc *>(pl.tab_scratch);
-    double *dstart = reinterpret_cast<double *>(pl.tab_scratch) + 4 * (size_t)ng;
-    static_assert(sizeof(GeomDesc) == 4 * sizeof(double), "geometry record");
-    pl.geom_host.resize(4 * (size_t)ng);
+    double *dstart = reinterpret_cast<double *>(pl.tab_scratch) + 5 * (size_t)ng;
+    static_assert(sizeof(GeomDesc) == 5 * sizeof(double), "geometry record");
+    pl.geom_host.resize(5 * (size_t)ng);
     std::memcpy(pl.geom_host.data(), geoms.data(), sizeof(GeomDesc) * ng);
     AXF_HIP(hipMemcpyAsync(dgeo, pl.geom_host.data(), sizeof(GeomDesc) * ng, hipMemcpyHostToDevice, st));
     // x columns and series of each geometry, handed to the r-derivative kernel
@@ -571,7 +579,7 @@ size_t table_scratch_doubles(int d, int M, int nmodes)
     const size_t L = 2 * (size_t)M + 1;
     const size_t nw1 = nmodes < 2 ? 2 : nmodes;   // modes 0..Nw of the x columns
     // geometries, starting columns, and the x columns + series in double-double
-    return 4 * ng + ng * (size_t)nmodes * 4 * L + ng * 2 * (nw1 + 8) * L;
+    return 5 * ng + ng * (size_t)nmodes * 4 * L + ng * 2 * (nw1 + 8) * L;
 }
 
 }  // namespace axf

@@ -505,6 +505,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     // (then every level's stations sit at the same box-unit radii and the
     // levels share one set of tables), else at the smallest radius
     pl.rlo = box[1] <= ext ? 0.0 : box[0];
+    pl.rmax = box[1];
     pl.zlo = box[2];
     pl.L = ext > 0.0 ? ext : 1.0;
     pl.invL = 1.0 / pl.L;

@@ -76,7 +76,16 @@ def test_tables_vs_oracle(geom, nmodes, M, depth, tol):
     for level in range(2, depth + 1):
         nb = 1 << level
         h = L / nb
-        for station in sorted({0, 1, nb // 2, nb - 1}):
+        # tables exist up to the station of the largest radius (of the finest
+        # level when the levels share them)
+        top = O.box_indices(np.array([r.max()]), np.array([0.0]), rlo, zlo, invL,
+                            depth if rlo == 0.0 else level)[0][0]
+        if top + 1 < nb:
+            with pytest.raises(axf.AxfError):
+                plan.table(level, int(top) + 1, 2, 0)
+        for station in sorted({0, 1, nb // 2, nb - 1, min(int(top), nb - 1)}):
+            if station > top:
+                continue
             for dr, dz in SEPS:
                 got = plan.table(level, station, dr, dz)
                 r_in = rlo + (station + 0.5) * h
