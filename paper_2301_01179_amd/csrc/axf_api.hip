@@ -186,17 +186,25 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         // same box-unit radii (s + 1/2), so a level's tables are the finest
         // level's first stations times 2^(l-d): only those are stored
         const bool shared = pl.rlo == 0.0;
-        const size_t ngeom = shared ? 12 * ((size_t)1 << d) : 12 * (((size_t)1 << (d + 1)) - 4);
+        // a level's tables cover the radial stations up to that of the
+        // largest radius: an S2L operator uses the table of the inner of two
+        // occupied stations, so stations beyond it are never read
+        size_t ngeom = 0;
+        for (int l = 2; l <= d; ++l) {
+            pl.tab_smax[l] = box_index(pl.rmax, pl.rlo, pl.invL, shared ? d : l);
+            pl.tab_base[l] = ngeom;
+            if (!shared || l == d) ngeom += (size_t)12 * (pl.tab_smax[l] + 1);
+        }
         Sizer tz;
         tz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
-        tz.add<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+        tz.add<double>(table_scratch_doubles(ngeom, pl.M, pl.nmodes));
         pl.tabmem = arena_acquire(tz.bytes + 4096);
         double *tab = pl.tabmem.take<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
         for (int l = 2; l <= d; ++l) {
-            pl.lev[l].tab = shared ? tab : tab + (size_t)12 * (((size_t)1 << l) - 4) * pl.nmodes * pl.TS;
+            pl.lev[l].tab = tab + pl.tab_base[l] * pl.nmodes * pl.TS;
             pl.lev[l].tscale = shared ? std::ldexp(1.0, l - d) : 1.0;
         }
-        pl.tab_scratch = pl.tabmem.take<double>(table_scratch_doubles(d, pl.M, pl.nmodes));
+        pl.tab_scratch = pl.tabmem.take<double>(table_scratch_doubles(ngeom, pl.M, pl.nmodes));
         // after everything the caller's stream already holds
         hipEvent_t ev = event_get(pl);
         AXF_HIP(hipEventRecord(ev, st));
@@ -242,9 +250,13 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     shift_coef_host(pl.M, pl.coef_host);
     AXF_HIP(hipMemcpyAsync(pl.shift_coef, pl.coef_host.data(), sizeof(double) * pl.coef_host.size(),
                            hipMemcpyHostToDevice, st));
-    // The tables may still be running on the table stream: the evaluation
-    // passes wait for `tables_ready` on their own stream just before the
-    // first S2L, so the gather, P2M and M2M overlap them.
+    // One wait for the tile and factor uploads (their host images can then
+    // go). The tables may still be running on the table stream: the
+    // evaluation passes wait for `tables_ready` on their own stream just
+    // before the first S2L, so the gather, P2M and M2M overlap them.
+    AXF_HIP(hipStreamSynchronize(st));
+    std::vector<char>().swap(pl.tile_host);
+    std::vector<int32_t>().swap(pl.box_host);
     pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes + pl.tabmem.bytes;
 }
 

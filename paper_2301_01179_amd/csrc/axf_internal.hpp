@@ -159,6 +159,7 @@ struct Plan {
     double rlo = 0, zlo = 0, L = 1, invL = 1;
     double rmax = 0;                     // largest ring radius of both sets
     int tab_smax[AXF_MAX_DEPTH + 1] = {};   // last radial station with tables, per level
+    size_t tab_base[AXF_MAX_DEPTH + 1] = {};   // first geometry of each level in the table storage
     double chistar = 1e300;
     Side src, fld;
     Level lev[AXF_MAX_DEPTH + 1];
@@ -171,6 +172,9 @@ struct Plan {
     hipEvent_t tables_ready = nullptr;   // recorded after the tables on the table stream
     double *shift_coef = nullptr;        // M2M and L2L factors, [3][2][S][S], S = AXF_MAX_ORDER + 1
     std::vector<double> coef_host;       // their host copy, source of an async copy
+    std::vector<int32_t> box_host;       // every level's occupied boxes of both sides (host copy)
+    size_t box_host_off[2][AXF_MAX_DEPTH + 1] = {};
+    std::vector<char> tile_host;         // host image of the S2L tile arena, source of an async copy
     int64_t near_pairs = 0, s2l_pairs = 0, s2l_units = 0;   // S2L: box pairs, (box, offset unit) pairs
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
@@ -205,7 +209,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
 void build_tiles(Plan &pl, hipStream_t st);
 // tables (axf_tables.hip)
 void build_tables(Plan &pl, hipStream_t st);
-size_t table_scratch_doubles(int d, int M, int nmodes);
+size_t table_scratch_doubles(size_t ngeom, int M, int nmodes);
 // shift factors of the M2M and L2L passes (axf_fmm.hip)
 constexpr int kCoefS = AXF_MAX_ORDER + 1;
 void shift_coef_host(int M, std::vector<double> &out);

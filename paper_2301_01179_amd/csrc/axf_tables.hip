@@ -518,18 +518,15 @@ void build_tables(Plan &pl, hipStream_t st)
 {
     const int M = pl.M, K = 2 * M, nm = pl.nmodes;
     // geometry list: level, station, separation (only the finest level when
-    // the levels share its tables: square on the axis).  A level's tables
-    // are built for the radial stations up to that of the largest radius:
-    // an S2L operator uses the table of the inner of two occupied stations,
-    // so stations beyond it are never read.  The plan keeps the list until
-    // the copy has run.
+    // the levels share its tables: square on the axis), for the stations
+    // 0..tab_smax[l] of each level, stored from geometry tab_base[l] on.
+    // The plan keeps the list until the copy has run.
     std::vector<GeomDesc> geoms;
     const bool shared = pl.rlo == 0.0;
-    for (int l = 2; l <= pl.d; ++l) pl.tab_smax[l] = box_index(pl.rmax, pl.rlo, pl.invL, shared ? pl.d : l);
     for (int l = shared ? pl.d : 2; l <= pl.d; ++l) {
         int nb = 1 << l;
         double h = pl.L / nb;
-        const size_t base = shared ? 0 : (size_t)12 * (((size_t)1 << l) - 4);
+        const size_t base = pl.tab_base[l];
         for (int s = 0; s <= pl.tab_smax[l]; ++s)
             for (int gs = 0; gs < 12; ++gs) {
                 int dr = gs < 4 ? gs / 2 : 2 + (gs - 4) / 4;
@@ -566,16 +563,14 @@ void build_tables(Plan &pl, hipStream_t st)
     k_tab_start<<<ng, kStartThreads, start_lds_bytes(M, nm), st>>>(M, nm, pl.chistar, dgeo, hand);
     const int ngr = (nm + kStartModes - 1) / kStartModes;
     k_tab_start_r<<<ng * ngr, kStartRThreads, start_r_lds_bytes(M, nm), st>>>(M, nm, dgeo, hand, dstart);
-    // tables of level l start at geometry index 12 * (2^l - 4)
-    double *tab = pl.lev[2].tab;
+    // every geometry record carries its slot from the storage's start
+    double *tab = pl.lev[2].tab - pl.tab_base[2] * (size_t)nm * TS;
     k_tab_laplace<<<ng * nm, kLapThreads, 0, st>>>(M, nm, dgeo, dstart, tab);
     AXF_HIP(hipGetLastError());
-    (void)TS;
 }
 
-size_t table_scratch_doubles(int d, int M, int nmodes)
+size_t table_scratch_doubles(size_t ng, int M, int nmodes)
 {
-    const size_t ng = 12 * (((size_t)1 << (d + 1)) - 4);
     const size_t L = 2 * (size_t)M + 1;
     const size_t nw1 = nmodes < 2 ? 2 : nmodes;   // modes 0..Nw of the x columns
     // geometries, starting columns, and the x columns + series in double-double

@@ -615,6 +615,22 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     unsigned long long h_cnt[4];
     AXF_HIP(hipMemcpyAsync(h_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipMemcpyAsync(h_cnt, cnt64, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+    // the occupied boxes of every level (the S2L tiles are made from them on
+    // the host) come back with the counts: one wait for both
+    {
+        size_t total = 0;
+        for (int side = 0; side < 2; ++side)
+            for (int l = 2; l <= d; ++l) {
+                pl.box_host_off[side][l] = total;
+                total += ins[side].s->nocc[l];
+            }
+        pl.box_host.resize(std::max<size_t>(total, 1));
+        for (int side = 0; side < 2; ++side)
+            for (int l = 2; l <= d; ++l)
+                if (ins[side].s->nocc[l])
+                    AXF_HIP(hipMemcpyAsync(pl.box_host.data() + pl.box_host_off[side][l], ins[side].s->box[l],
+                                           ins[side].s->nocc[l] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
     AXF_HIP(hipStreamSynchronize(st));
     pl.near_pairs = (int64_t)h_cnt[0];
     pl.s2l_pairs = (int64_t)h_cnt[1];
@@ -632,27 +648,13 @@ void build_tiles(Plan &pl, hipStream_t st)
     const int TB = s2l_tb(pl.M);
     Side *sides[2] = {&pl.src, &pl.fld};
     constexpr int NL = AXF_MAX_DEPTH + 1;
-    // every level's box list of both sides in one copy and one wait
-    std::vector<int32_t> hb;
-    size_t hoff[2][NL] = {}, total = 0;
-    for (int si = 0; si < 2; ++si)
-        for (int l = 2; l <= pl.d; ++l) {
-            hoff[si][l] = total;
-            total += sides[si]->nocc[l];
-        }
-    hb.resize(std::max<size_t>(total, 1));
-    for (int si = 0; si < 2; ++si)
-        for (int l = 2; l <= pl.d; ++l)
-            if (sides[si]->nocc[l])
-                AXF_HIP(hipMemcpyAsync(hb.data() + hoff[si][l], sides[si]->box[l],
-                                       sides[si]->nocc[l] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    AXF_HIP(hipStreamSynchronize(st));
+    // every level's box list of both sides, copied back with the tree counts
     std::vector<std::vector<int4>> tiles(2 * NL);
     std::vector<std::vector<int32_t>> slots(2 * NL);
     for (int si = 0; si < 2; ++si) {
         for (int l = 2; l <= pl.d; ++l) {
             const int n = sides[si]->nocc[l];
-            const int32_t *bx = hb.data() + hoff[si][l];
+            const int32_t *bx = pl.box_host.data() + pl.box_host_off[si][l];
             const int nb = 1 << l;
             auto &tv = tiles[si * NL + l];
             auto &sv = slots[si * NL + l];
@@ -679,8 +681,10 @@ void build_tiles(Plan &pl, hipStream_t st)
             sz.add<int32_t>(std::max<size_t>(1, slots[si * NL + l].size()));
         }
     pl.tilemem = arena_acquire(sz.bytes + 4096);
-    // the arena's image on the host, filled in place and copied once
-    std::vector<char> img(sz.bytes + 4096);
+    // the arena's image on the host, filled in place and copied once; the
+    // plan keeps it until the copy has run
+    std::vector<char> &img = pl.tile_host;
+    img.assign(sz.bytes + 4096, 0);
     for (int si = 0; si < 2; ++si) {
         Side &s = *sides[si];
         for (int l = 2; l <= pl.d; ++l) {
@@ -698,8 +702,6 @@ void build_tiles(Plan &pl, hipStream_t st)
     }
     if (pl.tilemem.used)
         AXF_HIP(hipMemcpyAsync(pl.tilemem.base, img.data(), pl.tilemem.used, hipMemcpyHostToDevice, st));
-    // the host image must outlive the copy
-    AXF_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace axf
