@@ -1115,14 +1115,29 @@ void launch_direct(Plan &pl, const Side &src, const Side &tgt, const EvalOut &ou
 // ------------------------------------------------------------- batches
 // Persistent kernels: each block walks the merged queue of (problem, item)
 // pairs of all problems of a batch, reading the problem's descriptor.
+// The descriptors are read through the constant address space: a pointer
+// read from ordinary memory is generic (flat), and the compiler would address
+// through it with flat instructions and 64-bit vector addresses, whereas a
+// pointer read from constant memory is taken to be global, as kernel-argument
+// pointers are (scalar base plus vector offset).
 constexpr int kPersistBlocks = 2048;
+typedef __attribute__((address_space(4))) const ProbDev ConstProbDev;
+__device__ __forceinline__ SideView view_of(const __attribute__((address_space(4))) SideView &v)
+{
+    SideView s;
+    s.r = v.r;
+    s.z = v.z;
+    s.perm = v.perm;
+    s.off = v.off;
+    return s;
+}
 
 __global__ __launch_bounds__(256) void kb_gather(const ProbDev *__restrict__ P, const int2 *__restrict__ q, int n,
                                                 int nmodes)
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         const int64_t e = (int64_t)it.y * 256 + threadIdx.x;
         if (e >= pd.ns * pd.Cs) continue;
         const int64_t pp = e / pd.Cs;
@@ -1136,9 +1151,9 @@ __global__ __launch_bounds__(256) void kb_p2m(const ProbDev *__restrict__ P, con
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         __syncthreads();
-        p2m_body(M, pd.C, pd.Cs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, pd.sv, pd.sbox[pd.d], pd.Sg,
+        p2m_body(M, pd.C, pd.Cs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, view_of(pd.sv), pd.sbox[pd.d], pd.Sg,
                  pd.mom[pd.d], it.y);
     }
 }
@@ -1148,7 +1163,7 @@ __global__ __launch_bounds__(256) void kb_m2m(const ProbDev *__restrict__ P, con
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         const int l = pd.d - t;
         __syncthreads();
         m2m_body(M, pd.C, l, pd.sbox[l], pd.sslot[l + 1], pd.mom[l + 1], pd.mom[l], pd.shift_coef, it.y);
@@ -1161,7 +1176,7 @@ __global__ __launch_bounds__(256) void kb_s2l(const ProbDev *__restrict__ P, con
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         __syncthreads();
         s2l_tile_body<LB, TB, MW, FIX>(M, nmodes, pd.nrhs, l, TS, pd.tiles[l], pd.tile_slots[l], pd.tbox[l], pd.sslot[l],
                               pd.mom[l], pd.tab[l], pd.loc[l], it.y, 1, nullptr, 0, pd.tscale[l]);
@@ -1173,7 +1188,7 @@ __global__ __launch_bounds__(256) void kb_l2l(const ProbDev *__restrict__ P, con
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         __syncthreads();
         l2l_body(M, pd.C, l, pd.tbox[l], l > 2 ? pd.tslot[l - 1] : nullptr, l > 2 ? pd.loc[l - 1] : nullptr,
                  pd.loc[l], pd.shift_coef, it.y);
@@ -1187,10 +1202,10 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
 {
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int2 it = q[i];
-        const ProbDev &pd = P[it.x];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         __syncthreads();
         leaf_body<NMB, 0>(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, chistar,
-                          pd.chunks, pd.tv, pd.sv, pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr, nullptr, nullptr,
+                          pd.chunks, view_of(pd.tv), view_of(pd.sv), pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr, nullptr, nullptr,
                           nullptr, nullptr, pd.nf, pd.Cs, it.y);
     }
 }

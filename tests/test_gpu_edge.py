@@ -179,3 +179,30 @@ def test_plan_on_other_stream(order):
     ref = O.fmm(rs, zs, rf, zf, S, M, plan.info()["depth"])
     assert rel_err(to_np(phi), ref).max() < TOL
     plan.close()
+
+
+@gpu
+def test_bitwise_reproducible():
+    """Every reduction runs in a fixed order (no floating-point atomics):
+    repeated evaluations, a second plan of the same points and repeated
+    adjoints give identical bits."""
+    need_gpu()
+    axf = _axf()
+    rs, zs, rf, zf, S = inputs.annulus(4000, 3000, 5, nrhs=2, seed=21)
+    St = torch.from_numpy(S).cuda()
+    p1 = axf.Plan(rs, zs, rf, zf, 5, 10, depth=4, nrhs=2)
+    p2 = axf.Plan(rs, zs, rf, zf, 5, 10, depth=4, nrhs=2)
+    a = p1.evaluate(St).clone()
+    b = p1.evaluate(St).clone()
+    c = p2.evaluate(St).clone()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    g = torch.from_numpy(np.conj(S[:, :, :1]) * np.ones((1, 1, rf.size))).cuda()
+    pa = axf.Plan(rs, zs, rf, zf, 5, 10, depth=4, nrhs=2)
+    out1 = [t.clone() for t in pa.adjoint(g, St)]
+    out2 = [t.clone() for t in pa.adjoint(g, St)]
+    for x, y in zip(out1, out2):
+        assert torch.equal(x, y)
+    ref = O.fmm(rs, zs, rf, zf, S, 10, 4)
+    assert rel_err(to_np(a), ref).max() < TOL
+    for p in (p1, p2, pa):
+        p.close()
