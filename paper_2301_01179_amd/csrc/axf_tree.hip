@@ -262,26 +262,57 @@ __device__ __forceinline__ int32_t box_count(const int32_t *__restrict__ off, in
     return off[(int64_t)(m + 1) << sh] - off[(int64_t)m << sh];
 }
 
-__global__ void k_flags(const int32_t *__restrict__ off, int level, int depth, int32_t *__restrict__ flag)
+// Occupancy flags of the levels 2..depth of both point sets in one array:
+// side 0 (sources) then side 1 (field points), each the levels in order,
+// level l holding its 4^l boxes (T = sum of 4^l entries per side).
+__global__ void k_flags_all(const int32_t *__restrict__ off0, const int32_t *__restrict__ off1, int depth,
+                            int64_t T, int32_t *__restrict__ flag)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    int nbox = 1 << (2 * level);
-    if (b >= nbox) return;
-    flag[b] = box_count(off, level, depth, b) > 0 ? 1 : 0;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 2 * T) return;
+    const int side = i >= T;
+    int64_t r = i - side * T, nbox = 16;
+    int l = 2;
+    while (r >= nbox) {
+        r -= nbox;
+        nbox <<= 2;
+        ++l;
+    }
+    flag[i] = box_count(side ? off1 : off0, l, depth, (int)r) > 0 ? 1 : 0;
 }
 
-__global__ void k_slots(const int32_t *__restrict__ flag, const int32_t *__restrict__ pre, int nbox,
-                        int32_t *__restrict__ slot, int32_t *__restrict__ box, int32_t *__restrict__ count)
+// From the exclusive scan `pre` of those flags: each level's slot map
+// (box -> compact index, -1 if empty), its occupied boxes in box order, and
+// its count (small[4 + 2 l + side]).  A side's slot maps sit back to back
+// from `slot` (level l at sum_{l' < l} 4^l'), its box lists from `box` (level l
+// at sum_{l' < l} min(4^l', n)).
+__global__ void k_slots_all(const int32_t *__restrict__ flag, const int32_t *__restrict__ pre, int64_t T,
+                            int64_t n0, int64_t n1, int32_t *__restrict__ slot0, int32_t *__restrict__ slot1,
+                            int32_t *__restrict__ box0, int32_t *__restrict__ box1, int32_t *__restrict__ small)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbox) return;
-    if (flag[b]) {
-        slot[b] = pre[b];
-        box[pre[b]] = b;
-    } else {
-        slot[b] = -1;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 2 * T) return;
+    const int side = i >= T;
+    const int64_t n = side ? n1 : n0;
+    int64_t r = i - side * T, nbox = 16, seg = 0, boff = 0;
+    int l = 2;
+    while (r >= nbox) {
+        r -= nbox;
+        seg += nbox;
+        boff += nbox < n ? nbox : n;
+        nbox <<= 2;
+        ++l;
     }
-    if (b == nbox - 1) *count = pre[b] + flag[b];
+    const int32_t rel = pre[i] - pre[side * T + seg];
+    int32_t *slot = (side ? slot1 : slot0) + seg;
+    int32_t *box = (side ? box1 : box0) + boff;
+    if (flag[i]) {
+        slot[r] = rel;
+        box[rel] = (int32_t)r;
+    } else {
+        slot[r] = -1;
+    }
+    if (r == nbox - 1) small[4 + 2 * l + side] = rel + flag[i];
 }
 
 __global__ void k_chunk_count(const int32_t *__restrict__ off, const int32_t *__restrict__ box, int nocc,
@@ -314,32 +345,49 @@ __global__ void k_chunk_fill(const int32_t *__restrict__ off, const int32_t *__r
 // Work counts: near-field pairs (targets x sources of the 3x3 neighbour
 // leaves) and S2L box pairs (occupied source boxes in each occupied target
 // box's interaction list).
+// Adds the block's per-thread counts v[0..1] to out[0..1]: summed in LDS,
+// then one global atomic per counter and block.  Every thread of the block
+// must call it.
+__device__ __forceinline__ void block_count_add(unsigned long long v0, unsigned long long v1,
+                                                unsigned long long *__restrict__ out, int nout)
+{
+    __shared__ unsigned long long acc[2];
+    if (threadIdx.x < 2) acc[threadIdx.x] = 0;
+    __syncthreads();
+    if (v0) atomicAdd(&acc[0], v0);
+    if (nout > 1 && v1) atomicAdd(&acc[1], v1);
+    __syncthreads();
+    if ((int)threadIdx.x < nout && acc[threadIdx.x]) atomicAdd(out + threadIdx.x, acc[threadIdx.x]);
+}
+
 __global__ void k_count_near(const int32_t *__restrict__ toff, const int32_t *__restrict__ soff,
                              const int32_t *__restrict__ tbox, int nocc, int depth,
                              unsigned long long *__restrict__ out)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nocc) return;
-    int nb = 1 << depth;
-    int b = tbox[k];
-    int ir = b / nb, iz = b - ir * nb;
-    long long nt = box_count(toff, depth, depth, b), ns = 0;
-    for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
-        for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) ns += box_count(soff, depth, depth, jr * nb + jz);
-    atomicAdd(out, (unsigned long long)(nt * ns));
+    long long nt = 0, ns = 0;
+    if (k < nocc) {
+        int nb = 1 << depth;
+        int b = tbox[k];
+        int ir = b / nb, iz = b - ir * nb;
+        nt = box_count(toff, depth, depth, b);
+        for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
+            for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz)
+                ns += box_count(soff, depth, depth, jr * nb + jz);
+    }
+    block_count_add((unsigned long long)(nt * ns), 0, out, 1);
 }
 
 __global__ void k_count_s2l(const int32_t *__restrict__ tbox, int nocc, const int32_t *__restrict__ sslot,
                             int level, unsigned long long *__restrict__ out)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nocc) return;
-    int nb = 1 << level;
-    int b = tbox[k];
-    int ir = b / nb, iz = b - ir * nb;
-    const int zlo = 2 * (iz >> 1) - 2, zhi = 2 * (iz >> 1) + 4;   // z window of the list
     int c = 0, u = 0;
-    for (int jr = 2 * (ir >> 1) - 2; jr < 2 * (ir >> 1) + 4; ++jr) {
+    const int nb = 1 << level;
+    const int b = k < nocc ? tbox[k] : 0;
+    const int ir = b / nb, iz = b - ir * nb;
+    const int zlo = 2 * (iz >> 1) - 2, zhi = 2 * (iz >> 1) + 4;   // z window of the list
+    for (int jr = 2 * (ir >> 1) - 2; k < nocc && jr < 2 * (ir >> 1) + 4; ++jr) {
         if (jr < 0 || jr >= nb) continue;
         const bool near_r = abs(jr - ir) <= 1;
         // offset units: source boxes at z distance +adz and -adz share one
@@ -358,8 +406,7 @@ __global__ void k_count_s2l(const int32_t *__restrict__ tbox, int nocc, const in
             u += occ;
         }
     }
-    atomicAdd(out, (unsigned long long)c);
-    atomicAdd(out + 1, (unsigned long long)u);
+    block_count_add((unsigned long long)c, (unsigned long long)u, out, 2);
 }
 
 inline int nblk(int64_t n, int b = kBlk) { return (int)((n + b - 1) / b); }
@@ -455,7 +502,9 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     sz.add<int32_t>(nmax);
     int64_t cnt_ints = 256 * ((nmax + kTile - 1) / kTile);
     sz.add<int32_t>(cnt_ints);
-    int64_t tmp_ints = std::max<int64_t>(scan_tmp_ints(cnt_ints), scan_tmp_ints((int64_t)1 << (2 * AXF_MAX_DEPTH)));
+    // scans: sort counts, chunk counts (<= 4^d) and the occupancy flags of
+    // every level of both sides (< 3 * 4^d)
+    int64_t tmp_ints = std::max<int64_t>(scan_tmp_ints(cnt_ints), scan_tmp_ints((int64_t)3 << (2 * AXF_MAX_DEPTH)));
     sz.add<int32_t>(tmp_ints);
     sz.add<int32_t>(64);
     sz.add<unsigned long long>(4);
@@ -550,32 +599,42 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     } ins[2] = {{&pl.src, rs, zs}, {&pl.fld, rf, zf}};
     // structure arena sized by depth
     const int64_t nleaf = (int64_t)1 << (2 * d);
+    // boxes of the levels 2..d (slot maps) and their occupied bound per side
+    int64_t tlev = 0, blev[2] = {0, 0};
+    for (int l = 2; l <= d; ++l) {
+        tlev += (int64_t)1 << (2 * l);
+        for (int side = 0; side < 2; ++side) blev[side] += std::min<int64_t>((int64_t)1 << (2 * l), ins[side].s->n);
+    }
+    const int64_t nflag = std::max<int64_t>(nleaf + 1, 2 * tlev);
     Sizer ss;
     for (int side = 0; side < 2; ++side) {
         int64_t n = ins[side].s->n;
         ss.add<int32_t>(nleaf + 1);
-        for (int l = 2; l <= d; ++l) {
-            ss.add<int32_t>((int64_t)1 << (2 * l));
-            ss.add<int32_t>(std::min<int64_t>((int64_t)1 << (2 * l), n));
-        }
+        ss.add<int32_t>(tlev);
+        ss.add<int32_t>(blev[side]);
         int64_t nocc_max = std::min<int64_t>(nleaf, n);
         ss.add<int4>(nocc_max + n / 64 + 1);
     }
-    ss.add<int32_t>(nleaf + 1);   // flags / chunk counts
-    ss.add<int32_t>(nleaf + 1);   // prefix
+    ss.add<int32_t>(nflag);   // flags / chunk counts
+    ss.add<int32_t>(nflag);   // prefix
     pl.tree = arena_acquire(ss.bytes + 4096);
     Arena &T = pl.tree;
     for (int side = 0; side < 2; ++side) {
         Side &s = *ins[side].s;
         s.off = T.take<int32_t>(nleaf + 1);
+        int32_t *slot_all = T.take<int32_t>(tlev);
+        int32_t *box_all = T.take<int32_t>(blev[side]);
+        int64_t so = 0, bo = 0;
         for (int l = 2; l <= d; ++l) {
-            s.slot[l] = T.take<int32_t>((int64_t)1 << (2 * l));
-            s.box[l] = T.take<int32_t>(std::min<int64_t>((int64_t)1 << (2 * l), s.n));
+            s.slot[l] = slot_all + so;
+            s.box[l] = box_all + bo;
+            so += (int64_t)1 << (2 * l);
+            bo += std::min<int64_t>((int64_t)1 << (2 * l), s.n);
         }
         s.chunks = T.take<int4>(std::min<int64_t>(nleaf, s.n) + s.n / 64 + 1);
     }
-    int32_t *flag = T.take<int32_t>(nleaf + 1);
-    int32_t *pre = T.take<int32_t>(nleaf + 1);
+    int32_t *flag = T.take<int32_t>(nflag);
+    int32_t *pre = T.take<int32_t>(nflag);
 
     // small[] layout: [0..1] maxleaf per side, [2..3] nchunks, [4 + 2*l + side] nocc
     AXF_HIP(hipMemsetAsync(small, 0, 64 * sizeof(int32_t), st));
@@ -587,13 +646,12 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
         AXF_HIP(hipMemcpyAsync(s.perm, sb.v0, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         k_gather_coords<<<nblk(n), kBlk, 0, st>>>(ins[side].r, ins[side].z, s.perm, n, s.r, s.z, s.rinv);
         k_offsets<<<nblk(nleaf + 1), kBlk, 0, st>>>(sb.k0, n, nleaf, s.off);
-        for (int l = 2; l <= d; ++l) {
-            int nbox = 1 << (2 * l);
-            k_flags<<<nblk(nbox), kBlk, 0, st>>>(s.off, l, d, flag);
-            scan_excl(flag, pre, nbox, sb.tmp, st);
-            k_slots<<<nblk(nbox), kBlk, 0, st>>>(flag, pre, nbox, s.slot[l], s.box[l], small + 4 + 2 * l + side);
-        }
     }
+    // occupied boxes of every level of both sides: one flag pass, one scan
+    k_flags_all<<<nblk(2 * tlev), kBlk, 0, st>>>(pl.src.off, pl.fld.off, d, tlev, flag);
+    scan_excl(flag, pre, 2 * tlev, sb.tmp, st);
+    k_slots_all<<<nblk(2 * tlev), kBlk, 0, st>>>(flag, pre, tlev, pl.src.n, pl.fld.n, pl.src.slot[2], pl.fld.slot[2],
+                                                 pl.src.box[2], pl.fld.box[2], small);
     // occupancy counts are needed to size the leaf work lists
     int32_t h_small[64];
     AXF_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
