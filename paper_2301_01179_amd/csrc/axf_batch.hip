@@ -239,7 +239,7 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             fill_probdev(pl, problems[i].S, problems[i].phi, pd[i]);
             int64_t ge = pl.src.n * pl.Cs;
             for (int64_t k = 0; k * 256 < ge; ++k) qg.push_back(make_int2(i, (int)k));
-            for (int k = 0; k < pl.src.nocc[pl.d] * pl.C; ++k) qp.push_back(make_int2(i, k));
+            for (int k = 0; k < pl.src.nocc[pl.d] * p2m_pairs(pl.C); ++k) qp.push_back(make_int2(i, k));
             for (int t = 1; pl.d - t >= 2; ++t)
                 for (int k = 0; k < pl.src.nocc[pl.d - t] * pl.C; ++k) qm[t].push_back(make_int2(i, k));
             for (int l = 2; l <= pl.d; ++l) {

@@ -37,7 +37,8 @@ __global__ void k_gather(const double2 *__restrict__ S, const int32_t *__restric
 
 // ------------------------------------------------------------------- P2M
 // Leaf moments (eq. analysis:moments in box units): one block per (leaf,
-// channel), s_ij = sum_s S_s (dr_s)^i (dz_s)^j / j!, offsets in leaf units.
+// pair of channels), s_ij = sum_s S_s (dr_s)^i (dz_s)^j / j!, offsets in leaf
+// units; the two channels share the staged powers of the offsets.
 constexpr int kP2MChunk = 64;
 __device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double rlo, double zlo, double invh,
                                          SideView sv, const int32_t *__restrict__ boxes,
@@ -45,9 +46,11 @@ __device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double
 {
     __shared__ double pr[kP2MChunk][AXF_MAX_ORDER + 1];
     __shared__ double pz[kP2MChunk][AXF_MAX_ORDER + 1];
-    __shared__ double2 ss[kP2MChunk];
+    __shared__ double2 ss[2][kP2MChunk];
     const int P = (M + 1) * (M + 2) / 2;
-    const int k = item / C, c = item - (item / C) * C;
+    const int npair = p2m_pairs(C);
+    const int k = item / npair, c = 2 * (item - (item / npair) * npair);
+    const bool two = c + 1 < C;     // uniform over the block
     const int b = boxes[k];
     const int nb = 1 << depth;
     const int ir = b / nb, iz = b - ir * nb;
@@ -68,6 +71,7 @@ __device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double
         oj[u] = p;
     }
     double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    double2 acc1[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
     for (int s0 = first; s0 < last; s0 += kP2MChunk) {
         const int ns = min(kP2MChunk, last - s0);
         __syncthreads();
@@ -82,26 +86,41 @@ __device__ __forceinline__ void p2m_body(int M, int C, int Cs, int depth, double
                 a *= dr;
                 q *= dz / (i + 1.0);
             }
-            ss[e] = Sg[(int64_t)(s0 + e) * Cs + c];
+            ss[0][e] = Sg[(int64_t)(s0 + e) * Cs + c];
+            ss[1][e] = two ? Sg[(int64_t)(s0 + e) * Cs + c + 1] : make_double2(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (threadIdx.x + u * 256 >= P) continue;
             const int i = oi[u], j = oj[u];
-            double2 a = acc[u];
-            for (int s = 0; s < ns; ++s) {
-                const double w = pr[s][i] * pz[s][j];
-                a.x = fma(w, ss[s].x, a.x);
-                a.y = fma(w, ss[s].y, a.y);
+            double2 a = acc[u], b = acc1[u];
+            if (two) {
+                for (int s = 0; s < ns; ++s) {
+                    const double w = pr[s][i] * pz[s][j];
+                    a.x = fma(w, ss[0][s].x, a.x);
+                    a.y = fma(w, ss[0][s].y, a.y);
+                    b.x = fma(w, ss[1][s].x, b.x);
+                    b.y = fma(w, ss[1][s].y, b.y);
+                }
+            } else {
+                for (int s = 0; s < ns; ++s) {
+                    const double w = pr[s][i] * pz[s][j];
+                    a.x = fma(w, ss[0][s].x, a.x);
+                    a.y = fma(w, ss[0][s].y, a.y);
+                }
             }
             acc[u] = a;
+            acc1[u] = b;
         }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int p = threadIdx.x + u * 256;
-        if (p < P) mom[((int64_t)k * C + c) * P + p] = acc[u];
+        if (p < P) {
+            mom[((int64_t)k * C + c) * P + p] = acc[u];
+            if (two) mom[((int64_t)k * C + c + 1) * P + p] = acc1[u];
+        }
     }
 }
 
@@ -1368,7 +1387,7 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
     SideView sv = view_of(src);
     if (src.nocc[d] > 0) {
         PhaseTimer tm(pl, st, AXF_PHASE_P2M);
-        k_p2m<<<src.nocc[d] * C, 256, 0, st>>>(M, C, pl.Cs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
+        k_p2m<<<src.nocc[d] * p2m_pairs(C), 256, 0, st>>>(M, C, pl.Cs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, sv, src.box[d],
                                            pl.Sg, pl.lev[d].mom);
     }
     {

@@ -116,6 +116,9 @@ inline int s2l_slots(int M, int lb)
 inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
 inline int s2l_tb(int) { return 4; }
+// P2M work items per leaf: one per pair of channels (the pair shares the
+// sources' offset powers).
+__host__ __device__ inline int p2m_pairs(int C) { return (C + 1) / 2; }
 // Window bound of the S2L lanes: M rounded up to a multiple of 4.
 inline int s2l_window(int M) { return M <= 4 ? 4 : (M + 3) / 4 * 4; }
 // Doubles past the last table: a lane reads its whole window, up to
