@@ -206,3 +206,21 @@ def test_bitwise_reproducible():
     assert rel_err(to_np(a), ref).max() < TOL
     for p in (p1, p2, pa):
         p.close()
+
+
+@gpu
+def test_max_depth():
+    """Depth 11, the library's limit: 4^11 leaves, almost every occupied leaf
+    holds a single ring; checked against the oracle's per-point FMM."""
+    need_gpu()
+    axf = _axf()
+    r, z, S = inputs.ring_box(1500, 2, seed=11)
+    plan = axf.Plan(r, z, r, z, 2, 4, depth=11)
+    assert plan.info()["depth"] == 11
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    idx = np.arange(0, 1500, 47)
+    ref = O.fmm_points(r, z, r, z, S, 4, 11, idx)
+    e = rel_err(phi[..., idx], ref).max()
+    print("depth 11 parity", e)
+    assert e < TOL
+    plan.close()
