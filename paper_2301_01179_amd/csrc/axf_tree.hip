@@ -14,8 +14,10 @@ namespace axf {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kItems = 8;                 // items per thread in scans / sort tiles
+constexpr int kItems = 8;                 // items per thread in scans
 constexpr int kTile = kBlk * kItems;      // 2048
+constexpr int kSortItems = 4;             // items per thread in radix-sort tiles
+constexpr int kSortTile = kBlk * kSortItems;   // 1024
 
 // ------------------------------------------------------------ bounding box
 __global__ void k_bbox_partial(const double *__restrict__ rs, const double *__restrict__ zs, int64_t ns,
@@ -167,8 +169,8 @@ __global__ void k_rs_hist(const uint32_t *__restrict__ key, int64_t n, int shift
     int t = threadIdx.x;
     h[t] = 0;
     __syncthreads();
-    int64_t base = blockIdx.x * (int64_t)kTile;
-    for (int k = t; k < kTile; k += kBlk) {
+    int64_t base = blockIdx.x * (int64_t)kSortTile;
+    for (int k = t; k < kSortTile; k += kBlk) {
         int64_t i = base + k;
         if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1);
     }
@@ -192,8 +194,8 @@ __global__ void k_rs_scatter(const uint32_t *__restrict__ key, const int32_t *__
     for (int k = 0; k < kBlk / 64; ++k) wcnt[k][t] = 0;
     __syncthreads();
     uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int round = 0; round < kItems; ++round) {
-        int64_t i = blockIdx.x * (int64_t)kTile + (int64_t)round * kBlk + t;
+    for (int round = 0; round < kSortItems; ++round) {
+        int64_t i = blockIdx.x * (int64_t)kSortTile + (int64_t)round * kBlk + t;
         bool act = i < n;
         uint32_t kk = act ? key[i] : 0u;
         int32_t vv = act ? val[i] : 0;
@@ -448,7 +450,7 @@ struct SortBufs {
 // Stable LSD radix sort of (key, val) on the low `bits` bits; result in k0/v0.
 void radix_sort(SortBufs &b, int64_t n, int bits, hipStream_t st)
 {
-    int nblocks = (int)((n + kTile - 1) / kTile);
+    int nblocks = (int)((n + kSortTile - 1) / kSortTile);
     uint32_t *ka = b.k0, *kb = b.k1;
     int32_t *va = b.v0, *vb = b.v1;
     for (int shift = 0; shift < bits; shift += 8) {
@@ -500,7 +502,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     sz.add<uint32_t>(nmax);
     sz.add<int32_t>(nmax);
     sz.add<int32_t>(nmax);
-    int64_t cnt_ints = 256 * ((nmax + kTile - 1) / kTile);
+    int64_t cnt_ints = 256 * ((nmax + kSortTile - 1) / kSortTile);
     sz.add<int32_t>(cnt_ints);
     // scans: sort counts, chunk counts (<= 4^d) and the occupancy flags of
     // every level of both sides (< 3 * 4^d)
