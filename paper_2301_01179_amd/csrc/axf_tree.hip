@@ -676,20 +676,22 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     AXF_HIP(hipMemcpyAsync(h_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipMemcpyAsync(h_cnt, cnt64, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
     // the occupied boxes of every level (the S2L tiles are made from them on
-    // the host) come back with the counts: one wait for both
+    // the host) come back with the counts: one wait for both, one copy per
+    // side (its box lists sit back to back, up to the last occupied box of
+    // the finest level)
     {
-        size_t total = 0;
-        for (int side = 0; side < 2; ++side)
-            for (int l = 2; l <= d; ++l) {
-                pl.box_host_off[side][l] = total;
-                total += ins[side].s->nocc[l];
-            }
+        size_t total = 0, base[2], len[2];
+        for (int side = 0; side < 2; ++side) {
+            const Side &s = *ins[side].s;
+            base[side] = total;
+            for (int l = 2; l <= d; ++l) pl.box_host_off[side][l] = total + (size_t)(s.box[l] - s.box[2]);
+            len[side] = (size_t)(s.box[d] - s.box[2]) + s.nocc[d];
+            total += len[side];
+        }
         pl.box_host.resize(std::max<size_t>(total, 1));
         for (int side = 0; side < 2; ++side)
-            for (int l = 2; l <= d; ++l)
-                if (ins[side].s->nocc[l])
-                    AXF_HIP(hipMemcpyAsync(pl.box_host.data() + pl.box_host_off[side][l], ins[side].s->box[l],
-                                           ins[side].s->nocc[l] * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            AXF_HIP(hipMemcpyAsync(pl.box_host.data() + base[side], ins[side].s->box[2], len[side] * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, st));
     }
     AXF_HIP(hipStreamSynchronize(st));
     pl.near_pairs = (int64_t)h_cnt[0];
