@@ -4,6 +4,7 @@
 #include <cstring>
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "axf_device.hpp"
@@ -14,6 +15,52 @@ namespace axf {
 namespace {
 
 constexpr int kBlk = 256;
+
+// Pinned host memory for the plan's readbacks.  A device-to-host copy into
+// pageable memory waits for its stream and then copies through a staging
+// buffer; into pinned memory it queues like any other copy, and the one
+// stream wait that follows covers all of them.  The buffers are pooled for
+// the life of the process (never freed, so no HIP call runs at exit).
+struct PinnedLease {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipStream_t st = nullptr;
+    static std::mutex &mu()
+    {
+        static std::mutex m;
+        return m;
+    }
+    static std::vector<std::pair<void *, size_t>> &pool()
+    {
+        static std::vector<std::pair<void *, size_t>> v;
+        return v;
+    }
+    PinnedLease(size_t bytes, hipStream_t s) : st(s)
+    {
+        {
+            std::lock_guard<std::mutex> lock(mu());
+            auto &v = pool();
+            for (size_t i = 0; i < v.size(); ++i)
+                if (v[i].second >= bytes) {
+                    p = v[i].first;
+                    cap = v[i].second;
+                    v.erase(v.begin() + (std::ptrdiff_t)i);
+                    return;
+                }
+        }
+        cap = std::max<size_t>(4096, (bytes + 4095) / 4096 * 4096);
+        AXF_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+    }
+    ~PinnedLease()
+    {
+        if (!p) return;
+        (void)hipStreamSynchronize(st);   // no copy into it may still be in flight
+        std::lock_guard<std::mutex> lock(mu());
+        pool().push_back({p, cap});
+    }
+    PinnedLease(const PinnedLease &) = delete;
+    PinnedLease &operator=(const PinnedLease &) = delete;
+};
 constexpr int kItems = 8;                 // items per thread in scans
 constexpr int kTile = kBlk * kItems;      // 2048
 constexpr int kSortItems = 4;             // items per thread in radix-sort tiles
@@ -545,9 +592,16 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     int nbb = std::min<int64_t>(1024, std::max<int64_t>(1, (ns + nf + kBlk - 1) / kBlk));
     k_bbox_partial<<<nbb, kBlk, 0, st>>>(rs, zs, ns, rf, zf, nf, bb);
     k_bbox_final<<<1, kBlk, 0, st>>>(bb, nbb, bb + 5 * 1024);
+    // pinned readback area: bounding box (5 doubles), the small counters
+    // (64 ints) and the pair counts (4 x 64 bits)
+    PinnedLease rb(1024, st);
+    double *pin_box = static_cast<double *>(rb.p);
+    int32_t *pin_small = reinterpret_cast<int32_t *>(static_cast<char *>(rb.p) + 64);
+    unsigned long long *pin_cnt = reinterpret_cast<unsigned long long *>(static_cast<char *>(rb.p) + 64 + 256);
     double box[5];
-    AXF_HIP(hipMemcpyAsync(box, bb + 5 * 1024, sizeof(box), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipMemcpyAsync(pin_box, bb + 5 * 1024, sizeof(box), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipStreamSynchronize(st));
+    std::memcpy(box, pin_box, sizeof(box));
     AXF_REQUIRE(box[4] == 0.0, AXF_ERR_INVALID_GEOMETRY,
                 "a coordinate is not finite or a ring radius is <= 0");
     double ext = std::max(box[1] - box[0], box[3] - box[2]);
@@ -656,8 +710,9 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
                                                  pl.src.box[2], pl.fld.box[2], small);
     // occupancy counts are needed to size the leaf work lists
     int32_t h_small[64];
-    AXF_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipMemcpyAsync(pin_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipStreamSynchronize(st));
+    std::memcpy(h_small, pin_small, sizeof(h_small));
     for (int side = 0; side < 2; ++side) {
         Side &s = *ins[side].s;
         for (int l = 2; l <= d; ++l) s.nocc[l] = h_small[4 + 2 * l + side];
@@ -673,8 +728,8 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
         k_count_s2l<<<nblk(pl.fld.nocc[l]), kBlk, 0, st>>>(pl.fld.box[l], pl.fld.nocc[l], pl.src.slot[l], l,
                                                            cnt64 + 1);
     unsigned long long h_cnt[4];
-    AXF_HIP(hipMemcpyAsync(h_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    AXF_HIP(hipMemcpyAsync(h_cnt, cnt64, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipMemcpyAsync(pin_small, small, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    AXF_HIP(hipMemcpyAsync(pin_cnt, cnt64, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
     // the occupied boxes of every level (the S2L tiles are made from them on
     // the host) come back with the counts: one wait for both, one copy per
     // side (its box lists sit back to back, up to the last occupied box of
@@ -689,11 +744,16 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
             total += len[side];
         }
         pl.box_host.resize(std::max<size_t>(total, 1));
+        PinnedLease bl(sizeof(int32_t) * pl.box_host.size(), st);
+        int32_t *pin_boxes = static_cast<int32_t *>(bl.p);
         for (int side = 0; side < 2; ++side)
-            AXF_HIP(hipMemcpyAsync(pl.box_host.data() + base[side], ins[side].s->box[2], len[side] * sizeof(int32_t),
+            AXF_HIP(hipMemcpyAsync(pin_boxes + base[side], ins[side].s->box[2], len[side] * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, st));
+        AXF_HIP(hipStreamSynchronize(st));
+        std::memcpy(pl.box_host.data(), pin_boxes, sizeof(int32_t) * total);
     }
-    AXF_HIP(hipStreamSynchronize(st));
+    std::memcpy(h_small, pin_small, 4 * sizeof(int32_t));
+    std::memcpy(h_cnt, pin_cnt, sizeof(h_cnt));
     pl.near_pairs = (int64_t)h_cnt[0];
     pl.s2l_pairs = (int64_t)h_cnt[1];
     pl.s2l_units = (int64_t)h_cnt[2];
