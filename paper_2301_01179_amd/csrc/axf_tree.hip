@@ -593,11 +593,12 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     k_bbox_partial<<<nbb, kBlk, 0, st>>>(rs, zs, ns, rf, zf, nf, bb);
     k_bbox_final<<<1, kBlk, 0, st>>>(bb, nbb, bb + 5 * 1024);
     // pinned readback area: bounding box (5 doubles), the small counters
-    // (64 ints) and the pair counts (4 x 64 bits)
+    // (64 ints), the pair counts (4 x 64 bits) and the depth rule's maximum
     PinnedLease rb(1024, st);
     double *pin_box = static_cast<double *>(rb.p);
     int32_t *pin_small = reinterpret_cast<int32_t *>(static_cast<char *>(rb.p) + 64);
     unsigned long long *pin_cnt = reinterpret_cast<unsigned long long *>(static_cast<char *>(rb.p) + 64 + 256);
+    int32_t *pin_max = reinterpret_cast<int32_t *>(static_cast<char *>(rb.p) + 512);
     double box[5];
     AXF_HIP(hipMemcpyAsync(pin_box, bb + 5 * 1024, sizeof(box), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipStreamSynchronize(st));
@@ -631,10 +632,9 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
             int g = (int)std::min<int64_t>(1024, (nl + kBlk - 1) / kBlk);
             k_max_int<<<g, kBlk, 0, st>>>(hs, nl, small);
             k_max_int<<<g, kBlk, 0, st>>>(hf, nl, small);
-            int32_t mx = 0;
-            AXF_HIP(hipMemcpyAsync(&mx, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            AXF_HIP(hipMemcpyAsync(pin_max, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             AXF_HIP(hipStreamSynchronize(st));
-            return (int)mx;
+            return (int)*pin_max;
         };
         double est = std::log((double)nmax / std::max(1, pl.p.max_leaf)) / std::log(4.0);
         d = std::max(2, std::min(AXF_MAX_DEPTH, (int)std::ceil(est)));
