@@ -94,7 +94,7 @@ def test_order_limits(M):
 def test_max_modes():
     need_gpu()
     r, z, S = inputs.ring_box(200, 64, seed=64)
-    _check(r, z, r, z, S, 5, 2, tol=1e-11)
+    _check(r, z, r, z, S, 5, 2)
 
 
 @gpu

@@ -86,6 +86,44 @@ def test_green_high_order_accuracy():
     assert worst < 5e-12, worst
 
 
+def _high_mode_points(N):
+    """chi - 1 values for the high-mode pins: a log grid over [1e-4, 0.05]
+    plus both sides of the paper's switch 1.008, of the growth-bound switch
+    e^(2 N eta) = e^(64 acosh 1.008), and of the switch where
+    N e^(2 N eta) = 2^13."""
+    pts = list(np.geomspace(1e-4, 0.05, 12))
+    etas = [math.acosh(1.008), 32 * math.acosh(1.008) / N,
+            (13 * math.log(2) - math.log(N)) / (2 * N)]
+    for eta in etas:
+        d = math.cosh(eta) - 1.0
+        pts += [d * (1 - 1e-3), d * (1 + 1e-3)]
+    return sorted(p for p in pts if p > 0)
+
+
+@pytest.mark.parametrize("N", [32, 48, 63])
+def test_green_high_modes(N):
+    """All modes up to N = 63 (the library accepts 64) against mpmath's
+    Legendre Q, across chi - 1 in [1e-4, 0.05] on both sides of every switch
+    point, at r = r1 and at r != r1: <= 5e-12 relative to G^(n)."""
+    worst = 0.0
+    for k, d in enumerate(_high_mode_points(N)):
+        if k % 2 == 0:
+            r, r1 = 1.0, 1.0
+            x = math.sqrt(2.0 * d)              # chi - 1 = x^2 / 2
+        else:
+            r, r1 = 1.2, 0.8                    # chi - 1 = (0.16 + x^2) / 1.92
+            x2 = 1.92 * d - 0.16
+            if x2 < 0:
+                r, r1, x2 = 1.0, 1.0, 2.0 * d
+            x = math.sqrt(x2)
+        G = O.green(N, r, r1, x)
+        for n in range(N + 1):
+            ref = float(g_legenq(n, r, r1, x))
+            worst = max(worst, abs(G[n] - ref) / abs(ref))
+    print("worst relative error", worst)
+    assert worst <= 5e-12, worst
+
+
 @pytest.mark.parametrize("geom", [(1.1, 0.9, 0.3), (1.0, 1.003, 0.01), (0.5, 1.5, 0.7)])
 def test_green_vs_ring_quadrature(geom):
     r, r1, x = geom
