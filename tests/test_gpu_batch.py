@@ -106,13 +106,17 @@ def test_batch_64_problems():
     for i, t in enumerate(b.outputs):
         assert rel_err(graph[i], to_np(t)).max() < 1e-14, i
     rng = np.random.default_rng(17)
-    for i in (int(np.argmin(sizes)), int(np.argsort(sizes)[32]), int(np.argmax(sizes))):
+    worst = 0.0
+    for i in range(len(probs)):            # implementation parity on every problem
         r, z, _, _, S = probs[i]
         idx = np.sort(rng.choice(r.size, 3, replace=False))
         ref_pts = O.fmm_points(r, z, r, z, S, M, depths[i], idx)
         e = (np.abs(graph[i][..., idx] - ref_pts).max(axis=-1) / np.abs(ref_pts).max(axis=-1)).max()
-        print("problem", i, "n", r.size, "depth", depths[i], "parity", e, flush=True)
-        assert e < TOL
+        worst = max(worst, e)
+        assert e < TOL, (i, r.size, depths[i], e)
+    print("parity, worst over the 64 problems", worst, flush=True)
+    for i in (int(np.argmin(sizes)), int(np.argsort(sizes)[32]), int(np.argmax(sizes))):
+        r, z, _, _, S = probs[i]
         samp = np.sort(rng.choice(r.size, 64, replace=False))
         ref = O.direct(r, z, r[samp], z[samp], S)
         eps = (np.abs(graph[i][..., samp] - ref).max(axis=-1) / np.abs(ref).max(axis=-1)).max()

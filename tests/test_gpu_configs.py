@@ -53,12 +53,35 @@ def test_annulus_50k_order12():
     assert eps < 5e-6
 
 
+def _heavy_leaf_points(rs, zs, rf, zf, depth, nleaves, per_leaf, rng):
+    """Field points from the nleaves fullest leaves (by field plus source
+    count) of the depth-d tree, per_leaf from each."""
+    rlo, zlo, L, invL = O.square_info(rs, zs, rf, zf)
+    nb = 1 << depth
+    ir, iz = O.box_indices(rs, zs, rlo, zlo, invL, depth)
+    jr, jz = O.box_indices(rf, zf, rlo, zlo, invL, depth)
+    fkey = jr.astype(np.int64) * nb + jz
+    count = np.bincount(ir.astype(np.int64) * nb + iz, minlength=nb * nb) \
+        + np.bincount(fkey, minlength=nb * nb)
+    count[np.bincount(fkey, minlength=nb * nb) == 0] = 0
+    picks = []
+    for leaf in np.argsort(count)[::-1][:nleaves]:
+        members = np.flatnonzero(fkey == leaf)
+        picks.append(rng.choice(members, min(per_leaf, members.size), replace=False))
+    return np.concatenate(picks), int(count.max())
+
+
 @gpu
-def test_annulus_50k_order24_meets_1e10():
+@pytest.mark.parametrize("depth", [5, 6])
+def test_annulus_50k_order24_meets_1e10(depth):
+    """The benchmark's trees: depth 5 (the fastest) and depth 6 (<= 64 points
+    of each set per leaf), M = 24.  Implementation parity at 64 field points,
+    half of them in the four fullest leaves; accuracy against the exact sum
+    at 500 sampled points."""
     need_gpu()
     axf = _axf()
     rs, zs, rf, zf, S = inputs.annulus(50000, 50000, 17, 1, seed=2)
-    plan = axf.Plan(rs, zs, rf, zf, 17, 24, depth=4)
+    plan = axf.Plan(rs, zs, rf, zf, 17, 24, depth=depth)
     phi = to_np(plan.evaluate(torch.from_numpy(S)))
     rng = np.random.default_rng(12)
     samp = np.sort(rng.choice(50000, 500, replace=False))
@@ -66,13 +89,21 @@ def test_annulus_50k_order24_meets_1e10():
     eps = _sampled_eps(phi[..., samp], ref)
     print("eps at M=24", eps)
     assert eps <= 1e-10
-    idx = samp[:16]
-    ref_pts = O.fmm_points(rs, zs, rf, zf, S, 24, 4, idx)
-    assert _sampled_eps(phi[..., idx], ref_pts) < TOL_IMPL
+    heavy, fullest = _heavy_leaf_points(rs, zs, rf, zf, depth, 4, 8, rng)
+    idx = np.unique(np.concatenate([heavy, samp[:32]]))
+    ref_pts = O.fmm_points(rs, zs, rf, zf, S, 24, depth, idx)
+    e = _sampled_eps(phi[..., idx], ref_pts)
+    print("depth", depth, "fullest leaf", fullest, "parity at", idx.size, "points", e)
+    assert e < TOL_IMPL
+    plan.close()
 
 
 @gpu
 def test_generator_curve_1m():
+    """1,000,000 rings on the jittered generator curve, modes 0..32, M = 16,
+    depth 8: implementation parity at 32 points, 16 of them in the four
+    fullest leaves (over 1,000 points each), and accuracy against the exact
+    sum at 400 points."""
     need_gpu()
     axf = _axf()
     r, z, S = inputs.generator_curve(1_000_000, 33, 1, seed=3)
@@ -83,10 +114,11 @@ def test_generator_curve_1m():
     phi = to_np(plan.evaluate(torch.from_numpy(S)))
     assert np.all(np.isfinite(phi))
     rng = np.random.default_rng(13)
-    idx = np.sort(rng.choice(r.size, 6, replace=False))
+    heavy, fullest = _heavy_leaf_points(r, z, r, z, depth, 4, 4, rng)
+    idx = np.unique(np.concatenate([heavy, rng.choice(r.size, 16, replace=False)]))
     ref_pts = O.fmm_points(r, z, r, z, S, 16, depth, idx)
     e = _sampled_eps(phi[..., idx], ref_pts)
-    print("implementation parity at 6 points", e)
+    print("fullest leaf", fullest, "implementation parity at", idx.size, "points", e)
     assert e < 1e-11
     # accuracy against the exact sum at sampled field points (GPU direct
     # at the sampled points, itself pinned to the oracle below)
@@ -130,3 +162,69 @@ def test_adjoint_200k():
     ez = np.abs(gz[samp] - dgz).max() / np.abs(dgz).max()
     print("vs oracle direct adjoint", eS, er, ez)
     assert eS < 1e-5 and er < 1e-4 and ez < 1e-4
+
+
+@gpu
+def test_adjoint_200k_finite_differences():
+    """Central finite differences of L = sum |phi - phi_target|^2 at 64
+    sampled rings of the 200,000-ring adjoint workload (M = 12, <= 32 points
+    per leaf).  Every ring is both a source and a field point, so a ring is
+    moved as both (moving only its source copy would re-admit the excluded
+    self pair, a log singularity): dL/dr_i = g_r[i] + Re sum conj(gphi_i)
+    dphi_i/dr, the adjoint's source-coordinate gradient plus the field
+    gradient at the ring, and likewise in z.  Rings whose box would change
+    at any level, or that fix the bounding square, are not sampled."""
+    need_gpu()
+    axf = _axf()
+    n = 200_000
+    r, z, S = inputs.ring_box(n, 17, 1, seed=5)
+    _, _, S_target = inputs.ring_box(n, 17, 1, seed=6)
+    M = 12
+    base = axf.Plan(r, z, r, z, 17, M, depth=0, max_leaf=32)
+    d = base.info()["depth"]
+    St = torch.from_numpy(S).cuda()
+    phi_t = base.evaluate(torch.from_numpy(S_target).cuda()).clone()
+    phi, dphi_r, dphi_z = base.evaluate_grad(St)
+    gphi = 2 * (phi - phi_t)
+    _, g_r, g_z = base.adjoint(gphi, St)
+    tot_r = g_r + torch.real(torch.conj(gphi) * dphi_r).sum(dim=(0, 1))
+    tot_z = g_z + torch.real(torch.conj(gphi) * dphi_z).sum(dim=(0, 1))
+    tot_r, tot_z = to_np(tot_r), to_np(tot_z)
+    base.close()
+
+    def loss(rr, zz):
+        p = axf.Plan(rr, zz, rr, zz, 17, M, depth=d)
+        v = (p.evaluate(St) - phi_t).abs().pow(2).sum().item()
+        p.close()
+        return v
+
+    h = 1e-6
+    rlo, zlo, L, invL = O.square_info(r, z, r, z)
+    rng = np.random.default_rng(15)
+    picked = []
+    for i in rng.permutation(n):
+        if len(picked) == 64:
+            break
+        step = h * max(abs(r[i]), 1.0)
+        if min(r[i] - r.min(), r.max() - r[i], z[i] - z.min(), z.max() - z[i]) < 4 * step:
+            continue
+        same = True
+        for dr_, dz_ in ((step, 0), (-step, 0), (0, step), (0, -step)):
+            for lev in range(2, d + 1):
+                a = O.box_indices(np.array([r[i]]), np.array([z[i]]), rlo, zlo, invL, lev)
+                b = O.box_indices(np.array([r[i] + dr_]), np.array([z[i] + dz_]), rlo, zlo, invL, lev)
+                same &= a[0][0] == b[0][0] and a[1][0] == b[1][0]
+        if same:
+            picked.append(i)
+    scale_r, scale_z = np.abs(tot_r).max(), np.abs(tot_z).max()
+    worst = 0.0
+    for i in picked:
+        step = h * max(abs(r[i]), 1.0)
+        e = np.zeros(n)
+        e[i] = step
+        fr = (loss(r + e, z) - loss(r - e, z)) / (2 * step)
+        fz = (loss(r, z + e) - loss(r, z - e)) / (2 * step)
+        worst = max(worst, abs(tot_r[i] - fr) / scale_r, abs(tot_z[i] - fz) / scale_z)
+    print("depth", d, "rings", len(picked), "worst FD deviation / max gradient", worst)
+    assert len(picked) == 64
+    assert worst <= 2e-6

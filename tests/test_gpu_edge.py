@@ -91,6 +91,28 @@ def test_order_limits(M):
 
 
 @gpu
+@pytest.mark.parametrize("M", [17, 20, 21, 22, 23])
+def test_s2l_orders(M):
+    """Orders 17..23 run the remaining compiled S2L shapes: window bound 20
+    with partial rows (17) and with exact rows (20), window bound 24 with one
+    column block per lane (21) and with two, whose windows run past the row
+    ends into the next row or the table padding (22, 23)."""
+    need_gpu()
+    r, z, S = inputs.ring_box(400, 3, nrhs=2, seed=170 + M)
+    _check(r, z, r, z, S, M, 3)
+
+
+@gpu
+@pytest.mark.parametrize("nmodes", [11, 20, 40])
+def test_mode_buckets(nmodes):
+    """11, 20 and 40 modes run the near-field kernels compiled for 12, 24 and
+    48 modes (strengths zero padded to the bucket)."""
+    need_gpu()
+    r, z, S = inputs.ring_box(350, nmodes, nrhs=1, seed=200 + nmodes)
+    _check(r, z, r, z, S, 6, 3)
+
+
+@gpu
 def test_max_modes():
     need_gpu()
     r, z, S = inputs.ring_box(200, 64, seed=64)
