@@ -38,7 +38,14 @@
  *   R7. The starting formulas of App. A (eq. gfunc:derivatives:x and its r,
  *       r1 and mixed companions) lose up to ~14 digits at high x order when
  *       n x / r is small; they are evaluated in binary128 here (the paper
- *       does not discuss their conditioning).
+ *       does not discuss their conditioning), and the Laplace recursion that
+ *       continues them runs in x87 extended precision.
+ *   R14. The azimuthal Fourier series (section 2, eqs. analysis:source and
+ *       analysis:phi) with K equally spaced samples theta_k = 2 pi k / K:
+ *       S^(n) = (1/K) sum_k s(theta_k) e^(-i n theta_k), exact for a real
+ *       source of modes |n| <= N when K >= 2N + 1; and
+ *       phi(theta) = Re Phi^(0) + 2 Re sum_{n >= 1} Phi^(n) e^(i n theta),
+ *       which is the series over n = -N..N with Phi^(-n) = conj(Phi^(n)).
  */
 #include <math.h>
 #include <quadmath.h>
@@ -455,7 +462,11 @@ void ora_gtable(int N, int M, double r, double r1, double x, double *T)
     int Nw = N < 1 ? 1 : N;      /* mode 1 is needed for n = 0 (g^(-1) = g^(1)) */
     int K = 2 * M;               /* highest x order */
     size_t per = (size_t)(M + 1) * (M + 1) * (2 * M + 1);
-    double *W = (double *)calloc(per * (size_t)(Nw + 1), sizeof(double));
+    /* the Laplace recursion runs in x87 extended precision (64-bit
+     * significand, reading R7): its rounding then stays well below that of
+     * an FP64 recursion, which reaches ~1e-12 of an order's scale at high
+     * modes */
+    long double *W = (long double *)calloc(per * (size_t)(Nw + 1), sizeof(long double));
     ora_q Gq[Nw + 1];
     ora_q rq = r, r1q = r1, xq = x;
     ora_green_q(Nw, rq, r1q, xq, Gq);
@@ -543,51 +554,52 @@ void ora_gtable(int N, int M, double r, double r1, double x, double *T)
 #define WI(n, a, b, c) W[(size_t)(n) * per + ((size_t)(a) * (M + 1) + (b)) * (2 * M + 1) + (c)]
     for (int n = 0; n <= Nw; ++n)
         for (int k = 0; k <= K; ++k) {
-            WI(n, 0, 0, k) = (double)GQ(g00, n, k);
+            WI(n, 0, 0, k) = (long double)GQ(g00, n, k);
             if (M >= 1 && k <= K - 1) {
-                WI(n, 1, 0, k) = (double)GQ(g10, n, k);
-                WI(n, 0, 1, k) = (double)GQ(g01, n, k);
+                WI(n, 1, 0, k) = (long double)GQ(g10, n, k);
+                WI(n, 0, 1, k) = (long double)GQ(g01, n, k);
             }
-            if (M >= 1 && k <= K - 2) WI(n, 1, 1, k) = (double)GQ(g11, n, k);
+            if (M >= 1 && k <= K - 2) WI(n, 1, 1, k) = (long double)GQ(g11, n, k);
         }
 #undef GQ
     free(g00);
     /* Laplace recursion (eq. gfunc:laplace, reading R1) in r for b = 0, 1,
      * then in r1 for all a. */
+    const long double rl = r, r1l = r1;
     for (int n = 0; n <= N; ++n) {
-        double n2 = (double)n * (double)n;
+        long double n2 = (long double)n * (long double)n;
         for (int j = 0; j <= 1 && j <= M; ++j)
             for (int i = 0; i + 2 <= M; ++i)
                 for (int k = 0; i + 2 + j + k <= K; ++k) {
-                    double s = 0.0, rp = 1.0 / r;   /* rp = r^-(u+1) */
+                    long double s = 0.0L, rp = 1.0L / rl;   /* rp = r^-(u+1) */
                     for (int u = 0; u <= i; ++u) {
-                        double sg = (u & 1) ? -1.0 : 1.0;
-                        s += sg * rp * ((u + 1) * n2 / r * WI(n, i - u, j, k)
+                        long double sg = (u & 1) ? -1.0L : 1.0L;
+                        s += sg * rp * ((u + 1) * n2 / rl * WI(n, i - u, j, k)
                                         - (i - u + 1) * WI(n, i - u + 1, j, k));
-                        rp /= r;
+                        rp /= rl;
                     }
-                    WI(n, i + 2, j, k) = s / ((i + 1.0) * (i + 2.0))
-                        - (k + 1.0) * (k + 2.0) / ((i + 1.0) * (i + 2.0)) * WI(n, i, j, k + 2);
+                    WI(n, i + 2, j, k) = s / ((i + 1.0L) * (i + 2.0L))
+                        - (k + 1.0L) * (k + 2.0L) / ((i + 1.0L) * (i + 2.0L)) * WI(n, i, j, k + 2);
                 }
         for (int j = 0; j + 2 <= M; ++j)
             for (int a = 0; a <= M; ++a)
                 for (int k = 0; a + j + 2 + k <= K; ++k) {
-                    double s = 0.0, rp = 1.0 / r1;
+                    long double s = 0.0L, rp = 1.0L / r1l;
                     for (int u = 0; u <= j; ++u) {
-                        double sg = (u & 1) ? -1.0 : 1.0;
-                        s += sg * rp * ((u + 1) * n2 / r1 * WI(n, a, j - u, k)
+                        long double sg = (u & 1) ? -1.0L : 1.0L;
+                        s += sg * rp * ((u + 1) * n2 / r1l * WI(n, a, j - u, k)
                                         - (j - u + 1) * WI(n, a, j - u + 1, k));
-                        rp /= r1;
+                        rp /= r1l;
                     }
-                    WI(n, a, j + 2, k) = s / ((j + 1.0) * (j + 2.0))
-                        - (k + 1.0) * (k + 2.0) / ((j + 1.0) * (j + 2.0)) * WI(n, a, j, k + 2);
+                    WI(n, a, j + 2, k) = s / ((j + 1.0L) * (j + 2.0L))
+                        - (k + 1.0L) * (k + 2.0L) / ((j + 1.0L) * (j + 2.0L)) * WI(n, a, j, k + 2);
                 }
     }
     for (int n = 0; n <= N; ++n)
         for (int a = 0; a <= M; ++a)
             for (int b = 0; b <= M; ++b)
                 for (int c = 0; c <= K; ++c)
-                    T[TIDX(n, a, b, c)] = (a + b + c <= K) ? WI(n, a, b, c) : 0.0;
+                    T[TIDX(n, a, b, c)] = (a + b + c <= K) ? (double)WI(n, a, b, c) : 0.0;
 #undef WI
     free(W);
 }
@@ -1041,4 +1053,50 @@ void ora_fmm_points(int64_t ns, const double *rs, const double *zs,
     }
     free(sir); free(siz);
     (void)nb;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Azimuthal analysis and synthesis (section 2, eqs. analysis:source and
+ * analysis:phi; reading R14).  Angles are reduced exactly: the phase of
+ * term (n, k) is 2 pi ((n k) mod K) / K. */
+
+/* samples: [nrhs][nrings][K] real values s(theta_k) on each ring;
+ * S: complex [nrhs][nmodes][nrings], modes n = 0..nmodes-1. */
+void ora_analysis(int64_t nrings, int K, int nmodes, int nrhs, const double *samples, double *S)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nrings; ++i)
+        for (int q = 0; q < nrhs; ++q) {
+            const double *s = samples + ((int64_t)q * nrings + i) * K;
+            for (int n = 0; n < nmodes; ++n) {
+                double re = 0.0, im = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    double t = 2.0 * ORA_PI * (double)(((int64_t)n * k) % K) / K;
+                    re += s[k] * cos(t);
+                    im -= s[k] * sin(t);
+                }
+                double *o = S + 2 * (((int64_t)q * nmodes + n) * nrings + i);
+                o[0] = re / K;
+                o[1] = im / K;
+            }
+        }
+}
+
+/* phi: complex [nrhs][nmodes][npts]; out: [nrhs][npts][K] real values
+ * phi(theta_k) at theta_k = 2 pi k / K. */
+void ora_synthesis(int64_t npts, int nmodes, int nrhs, const double *phi, int K, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < npts; ++j)
+        for (int q = 0; q < nrhs; ++q)
+            for (int k = 0; k < K; ++k) {
+                double v = phi[2 * ((int64_t)q * nmodes * npts + j)];     /* Re Phi^(0) */
+                for (int n = 1; n < nmodes; ++n) {
+                    const double *p = phi + 2 * (((int64_t)q * nmodes + n) * npts + j);
+                    double t = 2.0 * ORA_PI * (double)(((int64_t)n * k) % K) / K;
+                    v += 2.0 * (p[0] * cos(t) - p[1] * sin(t));
+                }
+                out[((int64_t)q * npts + j) * K + k] = v;
+            }
 }

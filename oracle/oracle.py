@@ -47,7 +47,9 @@ def _load():
     lib.ora_fmm_grad.argtypes = common + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     lib.ora_fmm_points.argtypes = common + [ctypes.c_int, ctypes.c_int, _i64,
                                             ctypes.POINTER(ctypes.c_int64), _dp]
-    for f in (lib.ora_qseq, lib.ora_green, lib.ora_direct, lib.ora_direct_grad,
+    lib.ora_analysis.argtypes = [_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+    lib.ora_synthesis.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+    for f in (lib.ora_analysis, lib.ora_synthesis, lib.ora_qseq, lib.ora_green, lib.ora_direct, lib.ora_direct_grad,
               lib.ora_direct_adjoint, lib.ora_gtable, lib.ora_square_info,
               lib.ora_box_indices, lib.ora_fmm, lib.ora_fmm_points, lib.ora_ellipke,
               lib.ora_fmm_grad):
@@ -211,3 +213,25 @@ def rel_err_per_mode(phi, ref):
     num = np.abs(phi - ref).max(axis=-1)
     den = np.abs(ref).max(axis=-1)
     return num / np.where(den > 0, den, 1.0)
+
+
+def analysis(samples, nmodes: int):
+    """Fourier coefficients S^(n), n = 0..nmodes-1, of real samples
+    [nrhs, nrings, K] at theta_k = 2 pi k / K -> complex [nrhs, nmodes, nrings]."""
+    lib = _load()
+    samples = _f64(samples)
+    nrhs, nrings, K = samples.shape
+    S = np.zeros((nrhs, nmodes, nrings), dtype=np.complex128)
+    lib.ora_analysis(nrings, K, nmodes, nrhs, _p(samples), _p(S))
+    return S
+
+
+def synthesis(phi, K: int):
+    """phi(theta_k) at theta_k = 2 pi k / K from the modes n >= 0 (complex
+    [nrhs, nmodes, npts]) with Phi^(-n) = conj(Phi^(n)) -> real [nrhs, npts, K]."""
+    lib = _load()
+    phi = _c128(phi)
+    nrhs, nmodes, npts = phi.shape
+    out = np.zeros((nrhs, npts, K))
+    lib.ora_synthesis(npts, nmodes, nrhs, _p(phi), K, _p(out))
+    return out
