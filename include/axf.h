@@ -50,7 +50,8 @@ typedef enum {
     AXF_ERR_INVALID_GEOMETRY = 2,  /* r <= 0, or a non-finite coordinate       */
     AXF_ERR_OUT_OF_MEMORY = 3,     /* device allocation failed                 */
     AXF_ERR_UNSUPPORTED = 4,       /* order, modes or depth beyond the limits  */
-    AXF_ERR_HIP = 5                /* a HIP runtime call failed                */
+    AXF_ERR_HIP = 5,               /* a HIP runtime call failed                */
+    AXF_ERR_WORKSPACE = 6          /* caller workspace too small or misaligned */
 } axf_status;
 
 /* Limits of the library. */
@@ -58,6 +59,7 @@ typedef enum {
 #define AXF_MAX_ORDER 24   /* expansion order M <= 24                   */
 #define AXF_MAX_DEPTH 11   /* tree depth d <= 11                        */
 #define AXF_MAX_RHS 8      /* right-hand sides per plan                 */
+#define AXF_MAX_ANGLES 2048 /* samples per ring of the azimuthal transforms */
 
 /* Plan parameters.
  *   n_modes : N + 1, modes n = 0..N (1 <= n_modes <= AXF_MAX_MODES).
@@ -88,16 +90,42 @@ typedef struct axf_plan axf_plan;   /* opaque; owned by the library */
  *   r_fld, z_fld : [nf] field points (device).  May alias the sources.
  * The plan copies what it needs; the coordinate buffers may be freed after
  * the call returns.  This call synchronises `stream` (it reads back the
- * bounding square and the tree occupancy) and allocates device memory.  The
- * tables are built on an internal stream of the library and may still be in
- * flight when the call returns: every later call that reads them waits for
- * them on its own stream (evaluations just before their first S2L pass).
+ * bounding square and the tree occupancy) and allocates device memory (the
+ * library's own, see axf_plan_set_workspace).  The tables are built on an
+ * internal stream of the library and may still be in flight when the call
+ * returns: every later call that reads them waits for them on its own stream
+ * (evaluations just before their first S2L pass).
+ *   workspace_bytes : host output (may be NULL), the device bytes that hold
+ *          every buffer of this plan (sorted points, tree, work lists,
+ *          tables, moments, locals and evaluation scratch), the size that
+ *          axf_plan_set_workspace needs.
  * Returns AXF_ERR_INVALID_GEOMETRY if any r <= 0 or any coordinate is not
  * finite; ns >= 1 and nf >= 1 are required. */
 axf_status axf_plan_create(const axf_params *params,
                            int64_t ns, const double *r_src, const double *z_src,
                            int64_t nf, const double *r_fld, const double *z_fld,
-                           void *stream, axf_plan **out_plan);
+                           void *stream, axf_plan **out_plan, size_t *workspace_bytes);
+
+/* Move every buffer of the plan into caller-owned device memory, e.g. a
+ * uint8 tensor of the caller's allocator: `workspace` (aligned to 256 bytes)
+ * of `bytes` >= the workspace_bytes that axf_plan_create reported.  The
+ * plan's contents are copied, its device pointers rebased, and the library's
+ * own memory for it released; from then on the plan reads and writes only
+ * the workspace (and the caller's inputs and outputs).  The caller keeps the
+ * workspace alive and untouched until axf_plan_destroy.  Synchronises the
+ * device (the plan's tables may still be in flight); no work that uses the
+ * plan may be pending.  Once per plan.  Returns AXF_ERR_WORKSPACE if the
+ * workspace is too small or misaligned (the plan is then unchanged). */
+axf_status axf_plan_set_workspace(axf_plan *plan, void *workspace, size_t bytes);
+
+/* Device memory that the library allocates for itself (plans without a
+ * caller workspace, batches) is returned to the runtime when released,
+ * unless this per-process cache is enabled: up to `bytes` of released
+ * blocks are then kept and reused by later plans of a similar size, so
+ * that creating plans in a loop calls no hipMalloc in the steady state.
+ * 0 (the default) disables the cache; lowering the limit frees cached
+ * blocks at once.  Cached blocks are invisible to other allocators. */
+axf_status axf_set_cache_limit(size_t bytes);
 
 /* Release the plan and its device memory (after pending work on the plan's
  * last stream has finished).  NULL is accepted. */
@@ -109,12 +137,18 @@ void axf_plan_destroy(axf_plan *plan);
  * nothing. */
 axf_status axf_evaluate(axf_plan *plan, const double *S, double *phi, void *stream);
 
-/* FMM evaluation that also returns the field gradient at the field points:
- * dphi_dr = dPhi/dr, dphi_dz = dPhi/dz, same layout as phi (each may be
- * NULL).  The far field is differentiated through the local expansion, the
- * near field through the first-derivative starting formulas of App. A. */
+/* FMM evaluation that also returns the field gradient at the field points,
+ * mode by mode: dphi_dr = dPhi^(n)/dr, dphi_dz = dPhi^(n)/dz and
+ * dphi_az = i n Phi^(n) / r, the coefficient of e^(i n theta) in
+ * (1/r) dphi/dtheta of the series of eq. analysis:phi; same layout as phi,
+ * each may be NULL.  Together they are the cylindrical components of
+ * grad phi (the velocity of a potential flow, or with the roles of the
+ * source components the Biot-Savart velocity the paper names as the
+ * motivation in section 1).  The far field is differentiated through the
+ * local expansion, the near field through the first-derivative starting
+ * formulas of App. A. */
 axf_status axf_evaluate_grad(axf_plan *plan, const double *S, double *phi,
-                             double *dphi_dr, double *dphi_dz, void *stream);
+                             double *dphi_dr, double *dphi_dz, double *dphi_az, void *stream);
 
 /* Direct O(ns * nf) modal sum (eq. analysis:sum) on the GPU, same
  * arguments and layout as axf_evaluate.  Uses only the plan's points. */
@@ -242,6 +276,32 @@ axf_status axf_batch_launch_plain(axf_batch *batch, void *stream);
 axf_status axf_batch_problem_depth(const axf_batch *batch, int32_t i, int32_t *depth);
 
 void axf_batch_destroy(axf_batch *batch);
+
+/* ---------------------------------------------------------------------- */
+/* Azimuthal analysis and synthesis (section 2): the ring source is a real
+ * Fourier series s(theta1) = sum_{n=-N..N} S^(n) e^(i n theta1) with
+ * S^(-n) = conj(S^(n)) (eq. analysis:source), and the potential is
+ * phi(r, theta, z) = sum_{n=-N..N} Phi^(n)(r, z) e^(i n theta) (eq.
+ * analysis:phi), Phi^(n) being what axf_evaluate returns for n = 0..N.
+ * Angles are theta_k = 2 pi k / K, k = 0..K-1.  Both calls are
+ * asynchronous on `stream`, allocate nothing and need no plan. */
+
+/* S^(n) = (1/K) sum_k s(theta_k) e^(-i n theta_k), n = 0..n_modes-1.
+ *   samples : real [nrhs][nrings][K] (each ring's samples contiguous).
+ *   S       : complex128 [nrhs][n_modes][nrings], overwritten (the layout of
+ *             axf_evaluate's strengths).
+ * Exact for a real source of modes |n| <= n_modes - 1, which requires
+ * K >= 2 n_modes - 1 (AXF_ERR_INVALID_ARGUMENT otherwise: higher modes would
+ * alias); K <= AXF_MAX_ANGLES. */
+axf_status axf_azimuthal_analysis(int64_t nrings, int32_t n_angles, int32_t n_modes, int32_t nrhs,
+                                  const double *samples, double *S, void *stream);
+
+/* phi(theta_k) = Re Phi^(0) + 2 Re sum_{n=1..n_modes-1} Phi^(n) e^(i n theta_k),
+ * the series of eq. analysis:phi with Phi^(-n) = conj(Phi^(n)).
+ *   phi : complex128 [nrhs][n_modes][npts] (axf_evaluate's output layout).
+ *   out : real [nrhs][npts][K], overwritten.  1 <= K <= AXF_MAX_ANGLES. */
+axf_status axf_azimuthal_synthesis(int64_t npts, int32_t n_modes, int32_t nrhs, const double *phi,
+                                   int32_t n_angles, double *out, void *stream);
 
 /* ---------------------------------------------------------------------- */
 const char *axf_status_string(axf_status status);

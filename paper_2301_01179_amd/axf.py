@@ -17,15 +17,17 @@ LIB_PATH = os.path.join(HERE, "libaxf.so")
 
 AXF_OK = 0
 _STATUS = {0: "AXF_OK", 1: "AXF_ERR_INVALID_ARGUMENT", 2: "AXF_ERR_INVALID_GEOMETRY",
-           3: "AXF_ERR_OUT_OF_MEMORY", 4: "AXF_ERR_UNSUPPORTED", 5: "AXF_ERR_HIP"}
+           3: "AXF_ERR_OUT_OF_MEMORY", 4: "AXF_ERR_UNSUPPORTED", 5: "AXF_ERR_HIP",
+           6: "AXF_ERR_WORKSPACE"}
 
 EXPORTED = [
-    "axf_plan_create", "axf_plan_destroy", "axf_evaluate", "axf_evaluate_grad",
+    "axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_plan_destroy",
+    "axf_evaluate", "axf_evaluate_grad",
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
     "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
     "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
-    "axf_plan_census",
+    "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis",
 ]
 
 PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l"]
@@ -64,11 +66,13 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER
-    lib.axf_plan_create.argtypes = [P(Params), i64, vp, vp, i64, vp, vp, vp, P(vp)]
+    lib.axf_plan_create.argtypes = [P(Params), i64, vp, vp, i64, vp, vp, vp, P(vp), P(ctypes.c_size_t)]
+    lib.axf_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.axf_set_cache_limit.argtypes = [ctypes.c_size_t]
     lib.axf_plan_destroy.argtypes = [vp]
     lib.axf_plan_destroy.restype = None
     lib.axf_evaluate.argtypes = [vp, vp, vp, vp]
-    lib.axf_evaluate_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.axf_evaluate_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.axf_evaluate_direct.argtypes = [vp, vp, vp, vp]
     lib.axf_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.axf_plan_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i64), P(i64),
@@ -89,11 +93,13 @@ def load_library(path: str = LIB_PATH):
     lib.axf_plan_work.argtypes = [vp, P(i64), P(i64), P(i64), P(ctypes.c_double)]
     lib.axf_plan_table.argtypes = [vp, i32, i32, i32, i32, P(ctypes.c_double)]
     lib.axf_plan_census.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double)]
-    for name in ("axf_plan_create", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
+    lib.axf_azimuthal_analysis.argtypes = [i64, i32, i32, i32, vp, vp, vp]
+    lib.axf_azimuthal_synthesis.argtypes = [i64, i32, i32, vp, i32, vp, vp]
+    for name in ("axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
                  "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
                  "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
-                 "axf_plan_census"):
+                 "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -117,16 +123,60 @@ def _coords(x, dev):
     return t.contiguous()
 
 
+def azimuthal_analysis(samples, n_modes: int):
+    """Fourier coefficients S^(n), n = 0..n_modes-1, of a real ring source
+    sampled at theta_k = 2 pi k / K: samples float64 [nrhs, nrings, K] on
+    the GPU -> complex128 [nrhs, n_modes, nrings]."""
+    lib = load_library()
+    x = samples.contiguous()
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError("samples must be a float64 tensor on the GPU")
+    nrhs, nrings, K = x.shape
+    S = torch.empty((nrhs, n_modes, nrings), dtype=torch.complex128, device=x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.axf_azimuthal_analysis(nrings, K, n_modes, nrhs, _ptr(x), _ptr(S), _stream()),
+               "axf_azimuthal_analysis")
+    return S
+
+
+def azimuthal_synthesis(phi, n_angles: int):
+    """phi(theta_k), k = 0..K-1, from the modes n >= 0 (complex128
+    [nrhs, n_modes, npts] on the GPU, Phi^(-n) = conj(Phi^(n))) -> float64
+    [nrhs, npts, K]."""
+    lib = load_library()
+    x = phi.contiguous()
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dtype != torch.complex128 or not x.is_cuda:
+        raise ValueError("phi must be a complex128 tensor on the GPU")
+    nrhs, nm, npts = x.shape
+    out = torch.empty((nrhs, npts, n_angles), dtype=torch.float64, device=x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.axf_azimuthal_synthesis(npts, nm, nrhs, _ptr(x), n_angles, _ptr(out), _stream()),
+               "axf_azimuthal_synthesis")
+    return out
+
+
+def set_cache_limit(nbytes: int):
+    """Let the library keep up to nbytes of released device blocks for reuse
+    by later plans (0, the default, returns them to the runtime at once)."""
+    _check(load_library().axf_set_cache_limit(int(nbytes)), "axf_set_cache_limit")
+
+
 class Plan:
     """Tree, tables and work lists for fixed source and field points.
 
     r_src, z_src, r_fld, z_fld: float64 tensors (or arrays) of ring radii and
     axial stations.  n_modes = N + 1, order = M, depth 0 = automatic with at
-    most max_leaf points per leaf.
+    most max_leaf points per leaf.  torch_workspace=True moves every buffer of
+    the plan into a uint8 tensor from PyTorch's allocator (kept as
+    `workspace`), so that PyTorch accounts for the plan's memory.
     """
 
     def __init__(self, r_src, z_src, r_fld, z_fld, n_modes: int, order: int, depth: int = 0,
-                 max_leaf: int = 64, nrhs: int = 1, device=None):
+                 max_leaf: int = 64, nrhs: int = 1, device=None, torch_workspace: bool = False):
         lib = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -136,17 +186,32 @@ class Plan:
         self.n_modes, self.order, self.nrhs = n_modes, order, nrhs
         p = Params(n_modes, order, depth, max_leaf, nrhs, 0)
         h = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
         with torch.cuda.device(dev):
             st = lib.axf_plan_create(ctypes.byref(p), self.ns, _ptr(rs), _ptr(zs), self.nf, _ptr(rf),
-                                     _ptr(zf), _stream(), ctypes.byref(h))
+                                     _ptr(zf), _stream(), ctypes.byref(h), ctypes.byref(wsb))
         _check(st, "axf_plan_create")
         self._h = h
         self._coords = (rs, zs, rf, zf)
+        self.workspace_bytes = wsb.value
+        self.workspace = None
+        if torch_workspace:
+            self.set_workspace(torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev))
+
+    def set_workspace(self, ws):
+        """Move the plan into the caller's uint8 device tensor ws (at least
+        workspace_bytes); the plan keeps a reference to it."""
+        if ws.dtype != torch.uint8 or ws.device != self.device or not ws.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the plan's device")
+        with torch.cuda.device(self.device):
+            _check(_lib.axf_plan_set_workspace(self._h, _ptr(ws), ws.numel()), "axf_plan_set_workspace")
+        self.workspace = ws
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.axf_plan_destroy(self._h)
             self._h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -230,12 +295,15 @@ class Plan:
         _check(_lib.axf_evaluate(self._h, _ptr(S), _ptr(phi), _stream()), "axf_evaluate")
         return phi
 
-    def evaluate_grad(self, S):
+    def evaluate_grad(self, S, azimuthal: bool = False):
+        """(phi, dphi/dr, dphi/dz) per mode, and with azimuthal=True also
+        i n phi / r, the mode coefficients of (1/r) dphi/dtheta."""
         S = self._strengths(S, self.ns)
         phi, dr, dz = self._out(self.nf), self._out(self.nf), self._out(self.nf)
-        _check(_lib.axf_evaluate_grad(self._h, _ptr(S), _ptr(phi), _ptr(dr), _ptr(dz), _stream()),
+        az = self._out(self.nf) if azimuthal else None
+        _check(_lib.axf_evaluate_grad(self._h, _ptr(S), _ptr(phi), _ptr(dr), _ptr(dz), _ptr(az), _stream()),
                "axf_evaluate_grad")
-        return phi, dr, dz
+        return (phi, dr, dz, az) if azimuthal else (phi, dr, dz)
 
     def evaluate_direct(self, S, out=None):
         S = self._strengths(S, self.ns)

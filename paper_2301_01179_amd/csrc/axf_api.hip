@@ -17,11 +17,27 @@ void set_error(const std::string &msg) { g_err = msg; }
 const char *get_error() { return g_err.c_str(); }
 
 // ---------------------------------------------------------- arena cache
+// The cache is off unless the caller opts in with axf_set_cache_limit: its
+// blocks are invisible to other allocators (PyTorch's included), so by
+// default a released arena goes straight back to the runtime.
 namespace {
 std::mutex g_cache_mu;
 std::vector<Arena> g_cache;
 size_t g_cached_bytes = 0;
-constexpr size_t kCacheLimit = size_t(32) << 30;
+size_t g_cache_limit = 0;
+
+// Frees cached blocks, largest first, until at most `limit` bytes remain.
+// Caller holds g_cache_mu.
+void cache_trim(size_t limit)
+{
+    std::sort(g_cache.begin(), g_cache.end(), [](const Arena &a, const Arena &b) { return a.bytes < b.bytes; });
+    while (g_cached_bytes > limit && !g_cache.empty()) {
+        Arena a = g_cache.back();
+        g_cache.pop_back();
+        g_cached_bytes -= a.bytes;
+        (void)hipFree(a.base);
+    }
+}
 }  // namespace
 
 Arena arena_acquire(size_t bytes)
@@ -73,7 +89,7 @@ void arena_release(Arena &a)
 {
     if (!a.base) return;
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    if (g_cached_bytes + a.bytes <= kCacheLimit) {
+    if (g_cached_bytes + a.bytes <= g_cache_limit) {
         g_cache.push_back(a);
         g_cached_bytes += a.bytes;
     } else {
@@ -260,13 +276,77 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     pl.device_bytes = pl.points.bytes + pl.tree.bytes + pl.expn.bytes + pl.tilemem.bytes + pl.tabmem.bytes;
 }
 
+// Moves every buffer of a plan into caller memory [ws, ws + bytes): the five
+// arenas are copied back to back (each at a 256-byte boundary), every
+// device pointer of the plan is rebased, and the arenas are released.
+// Synchronises the device first (the tables may still be in flight).
+size_t plan_workspace_bytes(const Plan &pl)
+{
+    const Arena *ar[5] = {&pl.points, &pl.tree, &pl.tilemem, &pl.expn, &pl.tabmem};
+    size_t need = 0;
+    for (const Arena *a : ar) need = ((need + 255) & ~size_t(255)) + a->used;
+    return need;
+}
+
+static void plan_relocate(Plan &pl, char *ws, size_t bytes)
+{
+    Arena *ar[5] = {&pl.points, &pl.tree, &pl.tilemem, &pl.expn, &pl.tabmem};
+    size_t off[5], need = 0;
+    for (int i = 0; i < 5; ++i) {
+        need = (need + 255) & ~size_t(255);
+        off[i] = need;
+        need += ar[i]->used;
+    }
+    AXF_REQUIRE(bytes >= need, AXF_ERR_WORKSPACE,
+                "workspace of " + std::to_string(bytes) + " bytes is smaller than the " + std::to_string(need) +
+                    " bytes the plan needs");
+    // every listed pointer must lie in an arena (or be null) ...
+    // (an end pointer, p == base + used, belongs to its arena only if no
+    // arena holds p strictly inside: two allocations may be adjacent)
+    auto owner = [&](const char *p) {
+        for (int i = 0; i < 5; ++i)
+            if (ar[i]->base && p >= ar[i]->base && p < ar[i]->base + ar[i]->used) return i;
+        for (int i = 0; i < 5; ++i)
+            if (ar[i]->base && p == ar[i]->base + ar[i]->used) return i;
+        return -1;
+    };
+    std::vector<const void *> fields;
+    bool stray = false;
+    plan_device_ptrs(pl, [&](char *&p, const void *field) {
+        fields.push_back(field);
+        if (p) stray |= owner(p) < 0;
+    });
+    AXF_REQUIRE(!stray, AXF_ERR_HIP, "internal: a plan pointer lies outside the plan's arenas");
+    // ... and no unlisted word of the plan may hold an arena address
+    for (Arena *a : ar) fields.push_back(&a->base);
+    std::sort(fields.begin(), fields.end());
+    const uintptr_t *w = reinterpret_cast<const uintptr_t *>(&pl);
+    for (size_t k = 0; k < sizeof(Plan) / sizeof(uintptr_t); ++k) {
+        const char *v = reinterpret_cast<const char *>(w[k]);
+        bool in_arena = false;
+        for (Arena *a : ar)
+            in_arena |= a->base && v >= a->base && v < a->base + a->bytes;
+        AXF_REQUIRE(!in_arena || std::binary_search(fields.begin(), fields.end(), (const void *)&w[k]), AXF_ERR_HIP,
+                    "internal: the plan holds an arena address that relocation does not know");
+    }
+    AXF_HIP(hipSetDevice(pl.device));
+    AXF_HIP(hipDeviceSynchronize());
+    for (int i = 0; i < 5; ++i)
+        if (ar[i]->used) AXF_HIP(hipMemcpy(ws + off[i], ar[i]->base, ar[i]->used, hipMemcpyDeviceToDevice));
+    plan_device_ptrs(pl, [&](char *&p, const void *) {
+        if (!p) return;
+        const int i = owner(p);
+        p = ws + off[i] + (p - ar[i]->base);
+    });
+    for (Arena *a : ar) arena_release(*a);
+    pl.external = true;
+    pl.device_bytes = need;
+}
+
 }  // namespace axf
 
 using namespace axf;
 
-struct axf_plan {
-    Plan pl;
-};
 
 #define AXF_TRY(...)                                        \
     try {                                                   \
@@ -286,12 +366,13 @@ extern "C" {
 
 axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r_src, const double *z_src,
                            int64_t nf, const double *r_fld, const double *z_fld, void *stream,
-                           axf_plan **out_plan)
+                           axf_plan **out_plan, size_t *workspace_bytes)
 {
     axf_plan *h = nullptr;
     try {
         AXF_REQUIRE(out_plan != nullptr, AXF_ERR_INVALID_ARGUMENT, "out_plan is NULL");
         *out_plan = nullptr;
+        if (workspace_bytes) *workspace_bytes = 0;
         validate_params(params);
         AXF_REQUIRE(ns >= 1 && nf >= 1, AXF_ERR_INVALID_ARGUMENT, "ns and nf must be >= 1");
         AXF_REQUIRE(ns < (int64_t(1) << 31) && nf < (int64_t(1) << 31), AXF_ERR_UNSUPPORTED,
@@ -299,6 +380,7 @@ axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r
         AXF_REQUIRE(r_src && z_src && r_fld && z_fld, AXF_ERR_INVALID_ARGUMENT, "a coordinate pointer is NULL");
         h = new axf_plan();
         plan_build(h->pl, *params, ns, r_src, z_src, nf, r_fld, z_fld, (hipStream_t)stream);
+        if (workspace_bytes) *workspace_bytes = plan_workspace_bytes(h->pl);
         *out_plan = h;
         return AXF_OK;
     } catch (const Fail &f) {
@@ -311,6 +393,26 @@ axf_status axf_plan_create(const axf_params *params, int64_t ns, const double *r
         set_error("host allocation failed");
         return AXF_ERR_OUT_OF_MEMORY;
     }
+}
+
+axf_status axf_plan_set_workspace(axf_plan *plan, void *workspace, size_t bytes)
+{
+    AXF_TRY({
+        AXF_REQUIRE(plan && workspace, AXF_ERR_INVALID_ARGUMENT, "plan and workspace must be non-NULL");
+        AXF_REQUIRE(!plan->pl.external, AXF_ERR_INVALID_ARGUMENT, "the plan already lives in a workspace");
+        AXF_REQUIRE(((uintptr_t)workspace & 255) == 0, AXF_ERR_WORKSPACE,
+                    "workspace must be aligned to 256 bytes");
+        plan_relocate(plan->pl, (char *)workspace, bytes);
+    })
+}
+
+axf_status axf_set_cache_limit(size_t bytes)
+{
+    AXF_TRY({
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache_limit = bytes;
+        cache_trim(bytes);
+    })
 }
 
 void axf_plan_destroy(axf_plan *plan)
@@ -331,7 +433,7 @@ axf_status axf_evaluate(axf_plan *plan, const double *S, double *phi, void *stre
 }
 
 axf_status axf_evaluate_grad(axf_plan *plan, const double *S, double *phi, double *dphi_dr, double *dphi_dz,
-                             void *stream)
+                             double *dphi_az, void *stream)
 {
     AXF_TRY({
         AXF_REQUIRE(plan && S && phi, AXF_ERR_INVALID_ARGUMENT, "plan, S and phi must be non-NULL");
@@ -339,6 +441,7 @@ axf_status axf_evaluate_grad(axf_plan *plan, const double *S, double *phi, doubl
         o.phi = phi;
         o.dr = dphi_dr;
         o.dz = dphi_dz;
+        o.daz = dphi_az;
         o.mode = 1;
         run_fmm(plan->pl, plan->pl.src, plan->pl.fld, S, o, (hipStream_t)stream);
     })
@@ -540,6 +643,7 @@ const char *axf_status_string(axf_status s)
     case AXF_ERR_OUT_OF_MEMORY: return "AXF_ERR_OUT_OF_MEMORY";
     case AXF_ERR_UNSUPPORTED: return "AXF_ERR_UNSUPPORTED";
     case AXF_ERR_HIP: return "AXF_ERR_HIP";
+    case AXF_ERR_WORKSPACE: return "AXF_ERR_WORKSPACE";
     }
     return "AXF_ERR_UNKNOWN";
 }

@@ -146,10 +146,6 @@ int autotune_depth(const axf_problem &pb, int M, int nmodes, hipStream_t st)
 
 using namespace axf;
 
-struct axf_plan {
-    Plan pl;
-};
-
 struct axf_batch {
     int device = 0;
     axf_params p{};

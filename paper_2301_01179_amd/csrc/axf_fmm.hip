@@ -855,7 +855,8 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
                                              SideView tv, SideView sv, const double *__restrict__ sinv,
                                              const double2 *__restrict__ Sg, const double2 *__restrict__ loc,
                                              double2 *__restrict__ phi, double2 *__restrict__ dphr,
-                                             double2 *__restrict__ dphz, const double2 *__restrict__ Sdot,
+                                             double2 *__restrict__ dphz, double2 *__restrict__ dpha,
+                                             const double2 *__restrict__ Sdot,
                                              double *__restrict__ gr, double *__restrict__ gz, int64_t ntot,
                                              int Cs, int item)
 {
@@ -962,6 +963,8 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
                     if constexpr (MODE == 1) {
                         if (dphr) dphr[o] = make_double2(A.rr_[n], A.ri_[n]);
                         if (dphz) dphz[o] = make_double2(A.zr_[n], A.zi_[n]);
+                        // (1/r) d/dtheta of the mode-n term: i n Phi^(n) / r
+                        if (dpha) dpha[o] = make_double2(-n * A.ai[n] * inv_r, n * A.ar[n] * inv_r);
                     }
                     if constexpr (MODE == 2) {
                         double2 sd = Sdot[o];
@@ -986,11 +989,12 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
     int M, int nmodes, int nrhs, int depth, double rlo, double zlo, double invh, double chistar,
     const int4 *__restrict__ chunks, SideView tv, SideView sv, const double *__restrict__ sinv,
     const double2 *__restrict__ Sg, const double2 *__restrict__ loc, double2 *__restrict__ phi,
-    double2 *__restrict__ dphr, double2 *__restrict__ dphz, const double2 *__restrict__ Sdot,
+    double2 *__restrict__ dphr, double2 *__restrict__ dphz, double2 *__restrict__ dpha,
+    const double2 *__restrict__ Sdot,
     double *__restrict__ gr, double *__restrict__ gz, int64_t ntot, int Cs)
 {
     leaf_body<NMB, MODE>(M, nmodes, nrhs, depth, rlo, zlo, invh, chistar, chunks, tv, sv, sinv, Sg, loc, phi, dphr,
-                         dphz, Sdot, gr, gz, ntot, Cs, blockIdx.x);
+                         dphz, dpha, Sdot, gr, gz, ntot, Cs, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- direct
@@ -1103,7 +1107,7 @@ void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut 
     k_leaf<NMB, MODE><<<tgt.nchunks, 64 * PairShape<NMB>::WPB, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
                                                      pl.chistar, tgt.chunks, tv, sv, src.rinv, pl.Sg, loc,
                                                      (double2 *)out.phi, (double2 *)out.dr, (double2 *)out.dz,
-                                                     (const double2 *)out.Sdot, out.gr, out.gz, tgt.n,
+                                                     (double2 *)out.daz, (const double2 *)out.Sdot, out.gr, out.gz, tgt.n,
                                                      NMB * pl.nrhs);
 }
 
@@ -1225,7 +1229,7 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
         __syncthreads();
         leaf_body<NMB, 0>(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, chistar,
                           pd.chunks, view_of(pd.tv), view_of(pd.sv), pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr, nullptr, nullptr,
-                          nullptr, nullptr, pd.nf, pd.Cs, it.y);
+                          nullptr, nullptr, nullptr, pd.nf, pd.Cs, it.y);
     }
 }
 

@@ -182,6 +182,7 @@ struct Plan {
     bool census_done = false;
     double census_near[4] = {}, census_direct[4] = {};
     size_t device_bytes = 0;
+    bool external = false;      // buffers live in a caller workspace (axf_plan_set_workspace)
     // phase timing (HIP events on the evaluation stream)
     bool timing = false;
     struct Mark {
@@ -191,6 +192,48 @@ struct Plan {
     std::vector<Mark> marks;
     std::vector<hipEvent_t> spare_events;
 };
+
+// Calls f(v, field) for every device pointer a plan holds into its arenas:
+// v is its value as a char pointer (a reference, so that f may rebase it)
+// and field the address of the member itself.  Relocating a plan into a
+// caller's workspace rebases exactly these; it also checks that no other
+// word of the plan holds an address inside an arena, so a pointer added to
+// the plan without being listed here is reported instead of left dangling.
+template <class T, class F>
+inline void visit_ptr(T *&p, F &f)
+{
+    char *c = reinterpret_cast<char *>(p);
+    f(c, (const void *)&p);
+    p = reinterpret_cast<T *>(c);
+}
+template <class F>
+void plan_device_ptrs(Plan &pl, F &&f)
+{
+    for (Side *s : {&pl.src, &pl.fld}) {
+        visit_ptr(s->r, f);
+        visit_ptr(s->z, f);
+        visit_ptr(s->rinv, f);
+        visit_ptr(s->perm, f);
+        visit_ptr(s->off, f);
+        visit_ptr(s->chunks, f);
+        for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
+            visit_ptr(s->slot[l], f);
+            visit_ptr(s->box[l], f);
+            visit_ptr(s->tiles[l], f);
+            visit_ptr(s->tile_slots[l], f);
+        }
+    }
+    for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
+        visit_ptr(pl.lev[l].mom, f);
+        visit_ptr(pl.lev[l].loc, f);
+        visit_ptr(pl.lev[l].tab, f);
+    }
+    visit_ptr(pl.Sg, f);
+    visit_ptr(pl.s2l_part, f);
+    visit_ptr(pl.gsum, f);
+    visit_ptr(pl.tab_scratch, f);
+    visit_ptr(pl.shift_coef, f);
+}
 
 // Records HIP events around a pass when the plan's timing is enabled.
 struct PhaseTimer {
@@ -225,6 +268,7 @@ struct EvalOut {
     double *phi = nullptr;       // complex [nrhs][nmodes][tgt.n], caller order
     double *dr = nullptr;        // gradient outputs (mode 1)
     double *dz = nullptr;
+    double *daz = nullptr;       // mode 1: (1/r) dPhi/dtheta = i n Phi^(n) / r
     const double *Sdot = nullptr;  // mode 2: caller-order strengths at the targets
     double *gr = nullptr, *gz = nullptr;
     int mode = 0;
@@ -277,3 +321,8 @@ void pair_census(Plan &pl, bool direct, double out[4], hipStream_t st);
 void run_batch(const BatchQueues &bq, hipStream_t st);
 
 }  // namespace axf
+
+// The opaque plan handle of the C ABI.
+struct axf_plan {
+    axf::Plan pl;
+};

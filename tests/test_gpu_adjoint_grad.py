@@ -43,12 +43,15 @@ def test_field_gradient(depth):
     r, z, rf, zf, S, _ = _setup()
     M = 9
     plan = _plan(r, z, rf, zf, 5, M, depth, 2)
-    phi, dr, dz = (to_np(t) for t in plan.evaluate_grad(torch.from_numpy(S)))
+    phi, dr, dz, az = (to_np(t) for t in plan.evaluate_grad(torch.from_numpy(S), azimuthal=True))
     p0, d0r, d0z = O.fmm_grad(r, z, rf, zf, S, M, depth)
-    for a, b in ((phi, p0), (dr, d0r), (dz, d0z)):
+    # (1/r) dphi/dtheta of the series of eq. analysis:phi, mode by mode
+    a0 = 1j * np.arange(5)[None, :, None] * p0 / rf[None, None, :]
+    for a, b in ((phi, p0), (dr, d0r), (dz, d0z), (az[:, 1:], a0[:, 1:])):
         e = rel_err(a, b)
         print("grad impl", e.max())
         assert e.max() < TOL
+    assert np.all(az[:, 0] == 0)
     gr, gz = O.direct_grad(r, z, rf, zf, S)
     assert rel_err(dr, gr).max() < 1e-4 and rel_err(dz, gz).max() < 1e-4
 

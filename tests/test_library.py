@@ -46,7 +46,7 @@ def test_bad_params_rejected_before_device_work(kw, status):
     p = _params(**kw)
     h = ctypes.c_void_p()
     dummy = ctypes.c_void_p(8)
-    st = lib.axf_plan_create(ctypes.byref(p), 10, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h))
+    st = lib.axf_plan_create(ctypes.byref(p), 10, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h), None)
     assert st == status
     assert h.value is None
     assert lib.axf_last_error().decode()
@@ -58,14 +58,16 @@ def test_null_and_size_errors():
     p = _params()
     h = ctypes.c_void_p()
     dummy = ctypes.c_void_p(8)
-    assert lib.axf_plan_create(None, 10, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h)) == 1
-    assert lib.axf_plan_create(ctypes.byref(p), 0, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h)) == 1
-    assert lib.axf_plan_create(ctypes.byref(p), 10, None, dummy, 10, dummy, dummy, None, ctypes.byref(h)) == 1
-    assert lib.axf_plan_create(ctypes.byref(p), 10, dummy, dummy, 10, dummy, dummy, None, None) == 1
+    assert lib.axf_plan_create(None, 10, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h), None) == 1
+    assert lib.axf_plan_create(ctypes.byref(p), 0, dummy, dummy, 10, dummy, dummy, None, ctypes.byref(h), None) == 1
+    assert lib.axf_plan_create(ctypes.byref(p), 10, None, dummy, 10, dummy, dummy, None, ctypes.byref(h), None) == 1
+    assert lib.axf_plan_create(ctypes.byref(p), 10, dummy, dummy, 10, dummy, dummy, None, None, None) == 1
     assert lib.axf_evaluate(None, dummy, dummy, None) == 1
     assert lib.axf_adjoint(None, None, dummy, dummy, None, None, None) == 1
+    assert lib.axf_plan_set_workspace(None, dummy, ctypes.c_size_t(1 << 20)) == 1
     lib.axf_plan_destroy(None)
     assert lib.axf_status_string(2) == b"AXF_ERR_INVALID_GEOMETRY"
+    assert lib.axf_status_string(6) == b"AXF_ERR_WORKSPACE"
 
 
 def test_mode_buckets_and_tile_widths_cover_limits():
