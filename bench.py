@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 200k-ring adjoint measurement")
+    ap.add_argument("--no-curve", action="store_true", help="skip the 1M-ring generator-curve measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -155,6 +156,108 @@ def _median_time(torch, fn, reps):
     return float(np.median(ts))
 
 
+def leaf_occupancy(info, coords_np):
+    """Largest number of sources and of field points in one leaf of the
+    plan's tree (box index floor(((v - lo) / L) 2^d), clamped)."""
+    rlo, zlo, L, invL = info["square"]
+    d = info["depth"]
+    nb = 1 << d
+    out = []
+    for r, z in (coords_np[:2], coords_np[2:]):
+        ir = np.clip(np.floor(((r - rlo) * invL) * nb).astype(np.int64), 0, nb - 1)
+        iz = np.clip(np.floor(((z - zlo) * invL) * nb).astype(np.int64), 0, nb - 1)
+        out.append(int(np.bincount(ir * nb + iz).max()))
+    return {"sources": out[0], "field_points": out[1]}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_single_thread(args, npts=250):
+    """The oracle's direct sum on one host thread (OMP_NUM_THREADS=1, in a
+    child process that touches no GPU), at npts sampled field points of the
+    same workload."""
+    import subprocess
+    code = (
+        "import sys, time, json, numpy as np; sys.path.insert(0, %r)\n"
+        "from oracle import oracle as O; from paper_2301_01179_amd import inputs\n"
+        "rs, zs, rf, zf, S = inputs.annulus(%d, %d, %d, 1, seed=%d)\n"
+        "idx = np.sort(np.random.default_rng(7).choice(rf.size, %d, replace=False))\n"
+        "t0 = time.perf_counter(); O.direct(rs, zs, rf[idx], zf[idx], S); t = time.perf_counter() - t0\n"
+        "print(json.dumps({'seconds': t}))\n"
+    ) % (ROOT, args.ns, args.nf, args.modes, args.seed, npts)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return None
+    t = json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+    return {"value": float(npts) * args.ns * args.modes / t, "cores": 1,
+            "sample": f"{npts} sampled field points x {args.ns} sources x {args.modes} modes ({t:.1f} s)"}
+
+
+def phase_roofline(timing, flops, reps):
+    """Model FP64 rate of each timed phase and the fraction of the FP64
+    vector peak; the dominant phase first."""
+    out = {}
+    for p, (ms, n) in timing.items():
+        if ms <= 0 or flops.get(p, 0.0) <= 0:
+            continue
+        tf = flops[p] / (ms / 1e3 / reps) / 1e12
+        out[p] = {"ms": round(ms / reps, 4), "model_tflops": round(tf, 3),
+                  "frac": round(tf / PEAK_FP64_VALU_TFLOPS, 4)}
+    return dict(sorted(out.items(), key=lambda kv: -kv[1]["ms"]))
+
+
+def measure_curve(torch, axf, inputs, dev):
+    """Generator-curve workload: 1,000,000 rings = field points on r = 1 +
+    0.3 cos t, z = 0.3 sin t + 0.05 N(0, 1), modes 0..32.  Error against the
+    GPU direct sum at 1,000 sampled field points (the direct sum is itself
+    checked against the oracle in the tests) at M = 16 and at increasing M up
+    to 24, stopping at the first M whose max-over-modes error is <= 1e-10;
+    plan + evaluate time of each, at the depth (7, 8 or 9) timed fastest at
+    M = 16."""
+    n, nm = 1_000_000, 33
+    r, z, S = inputs.generator_curve(n, nm, 1, seed=3)
+    rt, zt = torch.from_numpy(r).to(dev), torch.from_numpy(z).to(dev)
+    St = torch.from_numpy(S).to(dev)
+    samp = np.sort(np.random.default_rng(21).choice(n, 1000, replace=False))
+    dplan = axf.Plan(rt, zt, rt[samp], zt[samp], nm, 0, depth=2)
+    ref = dplan.evaluate_direct(St).cpu().numpy()
+    dplan.close()
+    units = float(n) * n * nm
+    depth = autotune_depth(torch, axf, (rt, zt, rt, zt), St, nm, 16, [7, 8, 9])
+    results = []
+    for M in (16, 20, 22, 24):
+        state = {}
+
+        def step():
+            p = axf.Plan(rt, zt, rt, zt, nm, M, depth=depth)
+            state["phi"] = p.evaluate(St)
+            state["info"] = p.info()
+            p.close()
+
+        step()
+        t = _median_time(torch, step, 3)
+        phi = state["phi"][..., samp].cpu().numpy()
+        eps = float((np.abs(phi - ref).max(axis=-1) / np.abs(ref).max(axis=-1)).max())
+        results.append({"order": M, "ms_per_step": t * 1e3, "value": units / t, "max_rel_err": eps})
+        if eps <= 1e-10:
+            break
+    occ = leaf_occupancy(state["info"], (r, z, r, z))
+    return {"workload": f"{n} rings = field points on the jittered generator curve, modes 0..{nm - 1}",
+            "depth": depth, "max_points_per_leaf": occ, "orders": results,
+            "meets_1e-10": any(x["max_rel_err"] <= 1e-10 for x in results),
+            "error_reference": "GPU direct sum at 1000 sampled field points",
+            "unit": "modal ring-pair interactions/s"}
+
+
 def measure_adjoint(torch, axf, inputs, dev):
     """Adjoint workload: 200,000 rings (sources = field points, ring-box
     geometry), modes 0..16, M = 12; loss sum |phi - phi_target|^2.  Times the
@@ -178,10 +281,32 @@ def measure_adjoint(torch, axf, inputs, dev):
     fwd(); adj()
     t_f = _median_time(torch, fwd, 5)
     t_a = _median_time(torch, adj, 5)
+    # per-phase model FP64 rates (HIP events on the launch stream); sources
+    # and field points are one set here, so the swapped FMM of the adjoint
+    # has the forward's work model (its leaf also forms the coordinate
+    # gradients, which the model leaves out)
+    flops = plan.work()["flops"]
+    reps = 5
+    plan.set_timing(True)
+    for _ in range(reps):
+        fwd()
+    roof_f = phase_roofline(plan.read_timing(), flops, reps)
+    for _ in range(reps):
+        adj()
+    roof_a = phase_roofline(plan.read_timing(), flops, reps)
+    plan.set_timing(False)
+    total = sum(flops[p] for p in ("p2m", "m2m", "s2l", "l2l", "leaf"))
     units = float(n) * n * nm
     out = {"workload": f"{n} rings = field points, ring box [0.5,1.5]x[-0.5,0.5], modes 0..{nm - 1}, M = {M}",
            "depth": plan.info()["depth"], "ms_forward": t_f * 1e3, "ms_adjoint": t_a * 1e3,
-           "adjoint_value": units / t_a, "unit": "modal ring-pair interactions/s"}
+           "adjoint_value": units / t_a, "unit": "modal ring-pair interactions/s",
+           "forward_roofline": {"model_tflops": round(total / t_f / 1e12, 3),
+                                "frac": round(total / t_f / 1e12 / PEAK_FP64_VALU_TFLOPS, 4),
+                                "phases": roof_f},
+           "adjoint_roofline": {"model_tflops": round(total / t_a / 1e12, 3),
+                                "frac": round(total / t_a / 1e12 / PEAK_FP64_VALU_TFLOPS, 4),
+                                "phases": roof_a,
+                                "note": "forward work model (potential part of the leaf only)"}}
     plan.close()
     return out
 
@@ -232,12 +357,16 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    # a step creates a new plan: let released plan memory be reused (the
+    # library's arena cache is off by default)
+    axf.set_cache_limit(16 << 30)
     nm = args.modes
     rs_np, zs_np, rf_np, zf_np, S_np = inputs.annulus(args.ns, args.nf, nm, 1, seed=args.seed)
     rs, zs = torch.from_numpy(rs_np).to(dev), torch.from_numpy(zs_np).to(dev)
     rf, zf = torch.from_numpy(rf_np).to(dev), torch.from_numpy(zf_np).to(dev)
     S = torch.from_numpy(S_np).to(dev)
     coords = (rs, zs, rf, zf)
+    coords_np = (rs_np, zs_np, rf_np, zf_np)
     ns, nf = args.ns, args.nf
     units = float(ns) * nf * nm
 
@@ -278,9 +407,10 @@ def main():
         t_cpu = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
         cpu = {"value": float(len(sample)) * ns * nm / t_cpu, "unit": "modal ring-pair interactions/s",
-               "cores": cores, "kind": "oracle",
+               "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"direct modal sum of the oracle at {len(sample)} sampled field points "
-                         f"x {ns} sources x {nm} modes ({t_cpu:.1f} s)"}
+                         f"x {ns} sources x {nm} modes ({t_cpu:.1f} s)",
+               "single_thread": oracle_single_thread(args)}
         num = np.abs(phi_s - ref_cpu).max(axis=-1)
         den = np.abs(ref_cpu).max(axis=-1)
         eps_oracle = (num / den).ravel()
@@ -317,7 +447,23 @@ def main():
                      "max_rel_err": float(e2), "fmm_vs_direct_speedup": t_direct / ts2}
         p2.close()
 
+    # the tree of config's leaf rule (<= max_leaf points of each set per leaf)
+    leaf_rule = None
+    rule_plan = axf.Plan(rs, zs, rf, zf, nm, 0, depth=0, max_leaf=args.max_leaf)
+    d_rule = rule_plan.info()["depth"]
+    rule_plan.close()
+    if d_rule != depth:
+        pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, max(3, args.steps // 2), 1)
+        phir_s = phir[..., sample].cpu().numpy()
+        refs = ref_cpu if eps_oracle is not None else ref_gpu_s
+        er = (np.abs(phir_s - refs).max(axis=-1) / np.abs(refs).max(axis=-1)).max()
+        leaf_rule = {"depth": d_rule, "max_points_per_leaf": leaf_occupancy(pr.info(), coords_np),
+                     "value": units / tsr, "ms_per_step": tsr * 1e3, "eval_only_value": units / ter,
+                     "max_rel_err": float(er)}
+        pr.close()
+
     adjoint = None if args.no_adjoint else measure_adjoint(torch, axf, inputs, dev)
+    curve = None if args.no_curve else measure_curve(torch, axf, inputs, dev)
     batch = None if args.no_batch else measure_batch(torch, axf, inputs, dev)
 
     line = {
@@ -330,8 +476,13 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"annulus: {ns} ring sources + {nf} distinct field points, r in [0.1,1], "
                                f"z in [-1,1], modes 0..{nm - 1}, complex N(0,1) strengths",
-                   "order": args.order, "depth": depth, "max_leaf_rule": args.max_leaf, "nrhs": 1,
-                   "step": "plan (tree + tables) + evaluate"},
+                   "order": args.order, "depth": depth,
+                   "depth_choice": "fastest of depths 3..7 (one timed plan + evaluate each)" if args.depth == 0
+                   else "given",
+                   "max_points_per_leaf": leaf_occupancy(info, coords_np), "nrhs": 1,
+                   "step": "plan (tree + tables) + evaluate",
+                   "memory": "library arena cache enabled (axf_set_cache_limit): a step's plan reuses the "
+                             "previous step's device blocks"},
         "max_rel_err": float(eps.max()),
         "meets_1e-10": bool(eps.max() <= 1e-10),
         "rel_err_per_mode": [float(f"{x:.3g}") for x in eps],
@@ -351,7 +502,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "config_order_result": secondary,
+        "leaf_rule_result": leaf_rule,
         "adjoint_result": adjoint,
+        "curve_result": curve,
         "batch_result": batch,
     }
     if eps_oracle is not None:
