@@ -137,6 +137,19 @@ void axf_plan_destroy(axf_plan *plan);
  * nothing. */
 axf_status axf_evaluate(axf_plan *plan, const double *S, double *phi, void *stream);
 
+/* axf_evaluate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same passes and the same result bit for bit, with the evaluation scratch
+ * (strengths in tree order, moments, locals, S2L partial sums) in a fixed
+ * device array of the library of 256 MiB per GPU, held from the library's
+ * load until the process ends, instead of the plan's memory.  Allocates
+ * nothing, records no timing events.  Returns AXF_ERR_UNSUPPORTED with a
+ * message when the plan's evaluation needs more scratch than the array
+ * holds (use axf_evaluate), AXF_ERR_INVALID_ARGUMENT when the plan's device
+ * is not the current one.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race. */
+axf_status axf_evaluate_noalloc(axf_plan *plan, const double *S, double *phi, void *stream);
+
 /* FMM evaluation that also returns the field gradient at the field points,
  * mode by mode: dphi_dr = dPhi^(n)/dr, dphi_dz = dPhi^(n)/dz and
  * dphi_az = i n Phi^(n) / r, the coefficient of e^(i n theta) in

@@ -22,7 +22,7 @@ _STATUS = {0: "AXF_OK", 1: "AXF_ERR_INVALID_ARGUMENT", 2: "AXF_ERR_INVALID_GEOME
 
 EXPORTED = [
     "axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_plan_destroy",
-    "axf_evaluate", "axf_evaluate_grad",
+    "axf_evaluate", "axf_evaluate_noalloc", "axf_evaluate_grad",
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
     "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH):
     lib.axf_plan_destroy.argtypes = [vp]
     lib.axf_plan_destroy.restype = None
     lib.axf_evaluate.argtypes = [vp, vp, vp, vp]
+    lib.axf_evaluate_noalloc.argtypes = [vp, vp, vp, vp]
     lib.axf_evaluate_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.axf_evaluate_direct.argtypes = [vp, vp, vp, vp]
     lib.axf_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -95,7 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.axf_plan_census.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double)]
     lib.axf_azimuthal_analysis.argtypes = [i64, i32, i32, i32, vp, vp, vp]
     lib.axf_azimuthal_synthesis.argtypes = [i64, i32, i32, vp, i32, vp, vp]
-    for name in ("axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_evaluate", "axf_evaluate_grad", "axf_evaluate_direct",
+    for name in ("axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_evaluate",
+                 "axf_evaluate_noalloc", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
                  "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
                  "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
@@ -294,6 +296,13 @@ class Plan:
         phi = self._out(self.nf) if out is None else out
         _check(_lib.axf_evaluate(self._h, _ptr(S), _ptr(phi), _stream()), "axf_evaluate")
         return phi
+
+    def evaluate_noalloc(self, S, out):
+        """axf_evaluate_noalloc: the evaluation with its scratch in the
+        library's fixed device array; `out` [nrhs, n_modes, nf] complex128 is
+        given by the caller, so the call allocates nothing."""
+        _check(_lib.axf_evaluate_noalloc(self._h, _ptr(S), _ptr(out), _stream()), "axf_evaluate_noalloc")
+        return out
 
     def evaluate_grad(self, S, azimuthal: bool = False):
         """(phi, dphi/dr, dphi/dz) per mode, and with azimuthal=True also
