@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--order", type=int, default=HEADLINE_ORDER)
-    ap.add_argument("--depth", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--depth", type=int, default=0, help="0 = autotuned (with the tile width)")
+    ap.add_argument("--tile", type=int, default=0, help="S2L tile width 2, 4 or 8; 0 = autotuned")
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--ns", type=int, default=50000)
     ap.add_argument("--nf", type=int, default=50000)
@@ -93,45 +94,47 @@ def read_traffic(phase, kernel_file="axf_fmm.hip"):
         return None
 
 
-def autotune_depth(torch, axf, coords, S, nmodes, order, candidates):
-    """Pick the depth with the shortest plan + evaluate time (one trial each)."""
+def autotune_depth(torch, axf, coords, S, nmodes, order, candidates, tiles=(4,)):
+    """Pick the (depth, S2L tile width) with the shortest plan + evaluate time
+    (the second of two trials each)."""
     rs, zs, rf, zf = coords
     best = None
     for d in candidates:
-        try:
-            for rep in range(2):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                plan = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=d)
-                plan.evaluate(S)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                plan.close()
-        except axf.AxfError:
-            continue
-        if best is None or dt < best[1]:
-            best = (d, dt)
-    return best[0]
+        for tb in tiles:
+            try:
+                for rep in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    plan = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=d, tile=tb)
+                    plan.evaluate(S)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    plan.close()
+            except axf.AxfError:
+                continue
+            if best is None or dt < best[2]:
+                best = (d, tb, dt)
+    return best[0], best[1]
 
 
-def measure(torch, axf, coords, S, nmodes, order, depth, steps, warmup):
+def measure(torch, axf, coords, S, nmodes, order, depth, steps, warmup, tile=0):
     rs, zs, rf, zf = coords
     ns, nf = rs.numel(), rf.numel()
     for _ in range(warmup):
-        p = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth)
+        p = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth, tile=tile)
         p.evaluate(S)
         p.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        p = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth)
+        p = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth, tile=tile)
         phi = p.evaluate(S)
         p.close()
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / steps
 
     # evaluation only, with per-phase HIP events on the launch stream
-    plan = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth)
+    plan = axf.Plan(rs, zs, rf, zf, nmodes, order, depth=depth, tile=tile)
     plan.evaluate(S)
     torch.cuda.synchronize()
     plan.set_timing(True)
@@ -232,7 +235,7 @@ def measure_curve(torch, axf, inputs, dev):
     ref = dplan.evaluate_direct(St).cpu().numpy()
     dplan.close()
     units = float(n) * n * nm
-    depth = autotune_depth(torch, axf, (rt, zt, rt, zt), St, nm, 16, [7, 8, 9])
+    depth, _ = autotune_depth(torch, axf, (rt, zt, rt, zt), St, nm, 16, [7, 8, 9])
     results = []
     for M in (16, 20, 22, 24):
         state = {}
@@ -295,7 +298,7 @@ def measure_adjoint(torch, axf, inputs, dev):
         adj()
     roof_a = phase_roofline(plan.read_timing(), flops, reps)
     plan.set_timing(False)
-    total = sum(flops[p] for p in ("p2m", "m2m", "s2l", "l2l", "leaf"))
+    total = sum(flops[p] for p in ("p2m", "m2m", "s2l", "l2l", "leaf", "l2p"))
     units = float(n) * n * nm
     out = {"workload": f"{n} rings = field points, ring box [0.5,1.5]x[-0.5,0.5], modes 0..{nm - 1}, M = {M}",
            "depth": plan.info()["depth"], "ms_forward": t_f * 1e3, "ms_adjoint": t_a * 1e3,
@@ -373,17 +376,17 @@ def main():
     rng = np.random.default_rng(args.seed + 1000)
     sample = np.sort(rng.choice(nf, size=min(args.sample, nf), replace=False))
 
-    depth = args.depth
+    depth, tile = args.depth, args.tile
     if depth == 0:
-        depth = autotune_depth(torch, axf, coords, S, nm, args.order, [3, 4, 5, 6, 7])
+        depth, tile = autotune_depth(torch, axf, coords, S, nm, args.order, [3, 4, 5, 6, 7],
+                                     (2, 4, 8) if tile == 0 else (tile,))
+    tile = tile or 4
 
     plan, phi, t_step, t_eval, timing = measure(torch, axf, coords, S, nm, args.order, depth,
-                                                args.steps, args.warmup)
+                                                args.steps, args.warmup, tile)
     info = plan.info()
     work = plan.work()
     census = plan.census()["near"]
-    P_ = (args.order + 1) * (args.order + 2) / 2
-    local_eval_flops = nf * (4.0 * P_ * nm + 2.0 * P_)        # local expansions at the field points
 
     # GPU direct sum (same points) for the speed-up
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -423,7 +426,7 @@ def main():
 
     # roofline of the dominant kernel (evaluation passes)
     flops = work["flops"]
-    phases = ["p2m", "m2m", "l2l", "s2l", "leaf"]
+    phases = ["p2m", "m2m", "l2l", "s2l", "leaf", "l2p"]
     dom = max(phases, key=lambda p: timing[p][0])
     ms_dom, launches = timing[dom]
     achieved = flops[dom] / (ms_dom / 1e3 / args.steps) / 1e12 if ms_dom > 0 else 0.0
@@ -436,13 +439,13 @@ def main():
 
     secondary = None
     if not args.no_secondary and args.order != CONFIG_ORDER:
-        d2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7])
+        d2, tb2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7], (2, 4, 8))
         p2, phi2, ts2, te2, _ = measure(torch, axf, coords, S, nm, CONFIG_ORDER, d2,
-                                        max(3, args.steps // 2), 1)
+                                        max(3, args.steps // 2), 1, tb2)
         phi2_s = phi2[..., sample].cpu().numpy()
         refs = ref_cpu if eps_oracle is not None else ref_gpu_s
         e2 = (np.abs(phi2_s - refs).max(axis=-1) / np.abs(refs).max(axis=-1)).max()
-        secondary = {"order": CONFIG_ORDER, "depth": d2, "value": units / ts2,
+        secondary = {"order": CONFIG_ORDER, "depth": d2, "tile": tb2, "value": units / ts2,
                      "eval_only_value": units / te2, "ms_per_step": ts2 * 1e3,
                      "max_rel_err": float(e2), "fmm_vs_direct_speedup": t_direct / ts2}
         p2.close()
@@ -453,7 +456,8 @@ def main():
     d_rule = rule_plan.info()["depth"]
     rule_plan.close()
     if d_rule != depth:
-        pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, max(3, args.steps // 2), 1)
+        pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, max(3, args.steps // 2), 1,
+                                        tile)
         phir_s = phir[..., sample].cpu().numpy()
         refs = ref_cpu if eps_oracle is not None else ref_gpu_s
         er = (np.abs(phir_s - refs).max(axis=-1) / np.abs(refs).max(axis=-1)).max()
@@ -476,9 +480,9 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"annulus: {ns} ring sources + {nf} distinct field points, r in [0.1,1], "
                                f"z in [-1,1], modes 0..{nm - 1}, complex N(0,1) strengths",
-                   "order": args.order, "depth": depth,
-                   "depth_choice": "fastest of depths 3..7 (one timed plan + evaluate each)" if args.depth == 0
-                   else "given",
+                   "order": args.order, "depth": depth, "s2l_tile": tile,
+                   "depth_choice": "fastest of depths 3..7 x S2L tile widths 2, 4, 8 (timed plan + evaluate)"
+                   if args.depth == 0 else "given",
                    "max_points_per_leaf": leaf_occupancy(info, coords_np), "nrhs": 1,
                    "step": "plan (tree + tables) + evaluate",
                    "memory": "library arena cache enabled (axf_set_cache_limit): a step's plan reuses the "
@@ -498,7 +502,7 @@ def main():
         "near_census": {"backward_fraction": census["backward"] / max(census["pairs"], 1.0),
                         "agm_iterations_per_pair": census["agm_iterations"] / max(census["pairs"], 1.0),
                         "recursion_steps_per_pair": census["steps"] / max(census["pairs"], 1.0),
-                        "model_flops_per_pair": (work["flops"]["leaf"] - local_eval_flops) / max(census["pairs"], 1.0)},
+                        "model_flops_per_pair": work["flops"]["leaf"] / max(census["pairs"], 1.0)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "config_order_result": secondary,

@@ -71,7 +71,14 @@ typedef enum {
  *             max_leaf field points in every leaf (capped at AXF_MAX_DEPTH).
  *   max_leaf: leaf bound used when depth == 0 (>= 1).
  *   nrhs    : right-hand sides sharing the geometry (1..AXF_MAX_RHS).
- *   flags   : reserved, pass 0. */
+ *   flags   : AXF_TILE(tb) selects the S2L tile width, the number of
+ *             same-parity target boxes of one radial station that share one
+ *             table read (section 2.2's operator reuse): 2, 4 or 8; 0 (no
+ *             flag) = 4.  Other bits must be 0. */
+#define AXF_TILE_SHIFT 8
+#define AXF_TILE_MASK (0xFu << AXF_TILE_SHIFT)
+#define AXF_TILE(tb) ((uint32_t)(tb) << AXF_TILE_SHIFT)
+
 typedef struct {
     int32_t n_modes;
     int32_t order;
@@ -219,7 +226,11 @@ enum {
     AXF_PHASE_LEAF = 4,    /* local expansion + near field at the leaves     */
     AXF_PHASE_DIRECT = 5,  /* direct modal sum                               */
     AXF_PHASE_L2L = 6,     /* downward pass: local shifts, eq. analysis:l2l  */
-    AXF_NUM_PHASES = 7
+    AXF_PHASE_L2P = 7,     /* local expansions at the field points, added to
+                              the near field (potential-only evaluations:
+                              their near field runs beside the downward pass
+                              and is timed as AXF_PHASE_LEAF)                */
+    AXF_NUM_PHASES = 8
 };
 axf_status axf_plan_set_timing(axf_plan *plan, int32_t enable);
 axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHASES] */,
@@ -237,7 +248,8 @@ axf_status axf_plan_read_timing(axf_plan *plan, double *ms /* host [AXF_NUM_PHAS
  * (sampled to about 3e7 pairs for the direct sum); P2M 4 P C + 2 P per
  * source; separable M2M 24 C(M+3, 3) per parent box and channel, L2L
  * 8 C(M+3, 3) per box and channel (AXF_PHASE_L2L); S2L 4 P^2 per unit and
- * channel; local evaluation 4 P C + 2 P per field point.  The census runs
+ * channel; local evaluation 4 P C + 2 P per field point (AXF_PHASE_L2P; the
+ * AXF_PHASE_LEAF entry counts the near-field pairs only).  The census runs
  * once, on the first call that asks for flops, and synchronises the device. */
 axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l_pairs, int64_t *s2l_units,
                          double *flops /* host [AXF_NUM_PHASES] */);
@@ -270,9 +282,15 @@ typedef struct axf_batch axf_batch;
 /* Build the batch: per-problem trees and tables, merged work queues, and
  * the captured graph.  params->nrhs and params->depth are ignored (taken per
  * problem); params->max_leaf is used where a problem's depth is 0 and the
- * autotuner is disabled (flags bit AXF_BATCH_NO_AUTOTUNE).  The problem
- * array is host memory and is copied; the S and phi buffers it names must
- * stay valid for every launch.  Synchronises `stream`. */
+ * autotuner is disabled (flags bit AXF_BATCH_NO_AUTOTUNE).  The autotuner
+ * measures, on the device, the seconds per near-field pair, per S2L unit,
+ * per shifted box and per point of a probe problem (once per process for a
+ * given order, mode count and tile width), takes the S2L tile width whose
+ * probe ran fastest unless params->flags holds AXF_TILE(tb) (one width for
+ * the whole batch), and gives every problem of depth 0 the depth of least
+ * modelled time over its exactly counted work.  The problem array is host
+ * memory and is copied; the S and phi buffers it names must stay valid for
+ * every launch.  Synchronises `stream`. */
 #define AXF_BATCH_NO_AUTOTUNE 1u
 axf_status axf_batch_create(const axf_params *params, int32_t nprob,
                             const axf_problem *problems, void *stream,
@@ -287,6 +305,9 @@ axf_status axf_batch_launch_plain(axf_batch *batch, void *stream);
 
 /* Depth the batch chose for problem `i` (host output). */
 axf_status axf_batch_problem_depth(const axf_batch *batch, int32_t i, int32_t *depth);
+
+/* S2L tile width the batch runs with (host output). */
+axf_status axf_batch_tile(const axf_batch *batch, int32_t *tile);
 
 void axf_batch_destroy(axf_batch *batch);
 

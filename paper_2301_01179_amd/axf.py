@@ -25,12 +25,14 @@ EXPORTED = [
     "axf_evaluate", "axf_evaluate_noalloc", "axf_evaluate_grad",
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
-    "axf_batch_problem_depth", "axf_batch_destroy", "axf_status_string", "axf_last_error",
+    "axf_batch_problem_depth", "axf_batch_tile", "axf_batch_destroy", "axf_status_string", "axf_last_error",
     "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
     "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis",
 ]
 
-PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l"]
+TILE_SHIFT = 8          # AXF_TILE(tb): S2L tile width in params.flags
+
+PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l", "l2p"]
 
 
 class AxfError(RuntimeError):
@@ -83,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.axf_batch_launch.argtypes = [vp, vp]
     lib.axf_batch_launch_plain.argtypes = [vp, vp]
     lib.axf_batch_problem_depth.argtypes = [vp, i32, P(i32)]
+    lib.axf_batch_tile.argtypes = [vp, P(i32)]
     lib.axf_batch_destroy.argtypes = [vp]
     lib.axf_batch_destroy.restype = None
     lib.axf_status_string.argtypes = [ctypes.c_int]
@@ -99,7 +102,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_evaluate",
                  "axf_evaluate_noalloc", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
-                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth",
+                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth", "axf_batch_tile",
                  "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
                  "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis"):
         getattr(lib, name).restype = ctypes.c_int
@@ -172,13 +175,15 @@ class Plan:
 
     r_src, z_src, r_fld, z_fld: float64 tensors (or arrays) of ring radii and
     axial stations.  n_modes = N + 1, order = M, depth 0 = automatic with at
-    most max_leaf points per leaf.  torch_workspace=True moves every buffer of
+    most max_leaf points per leaf; tile = S2L tile width 2, 4 or 8 (0: 4).
+    torch_workspace=True moves every buffer of
     the plan into a uint8 tensor from PyTorch's allocator (kept as
     `workspace`), so that PyTorch accounts for the plan's memory.
     """
 
     def __init__(self, r_src, z_src, r_fld, z_fld, n_modes: int, order: int, depth: int = 0,
-                 max_leaf: int = 64, nrhs: int = 1, device=None, torch_workspace: bool = False):
+                 max_leaf: int = 64, nrhs: int = 1, device=None, torch_workspace: bool = False,
+                 tile: int = 0):
         lib = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -186,7 +191,7 @@ class Plan:
         rf, zf = _coords(r_fld, dev), _coords(z_fld, dev)
         self.ns, self.nf = rs.numel(), rf.numel()
         self.n_modes, self.order, self.nrhs = n_modes, order, nrhs
-        p = Params(n_modes, order, depth, max_leaf, nrhs, 0)
+        p = Params(n_modes, order, depth, max_leaf, nrhs, tile << TILE_SHIFT)
         h = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
         with torch.cuda.device(dev):
@@ -349,7 +354,7 @@ class Batch:
     """
 
     def __init__(self, problems, n_modes: int, order: int, max_leaf: int = 64,
-                 autotune: bool = True, device=None):
+                 autotune: bool = True, device=None, tile: int = 0):
         lib = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -374,7 +379,7 @@ class Batch:
             self._keep.append((rs, zs, rf, zf))
             self.strengths.append(S)
             self.outputs.append(phi)
-        p = Params(n_modes, order, 0, max_leaf, 1, 0 if autotune else 1)
+        p = Params(n_modes, order, 0, max_leaf, 1, (0 if autotune else 1) | (tile << TILE_SHIFT))
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
             st = lib.axf_batch_create(ctypes.byref(p), len(problems), arr, _stream(), ctypes.byref(h))
@@ -398,6 +403,12 @@ class Batch:
             _check(_lib.axf_batch_problem_depth(self._h, i, ctypes.byref(d)), "axf_batch_problem_depth")
             out.append(d.value)
         return out
+
+    def tile(self) -> int:
+        """S2L tile width the batch runs with."""
+        t = ctypes.c_int32()
+        _check(_lib.axf_batch_tile(self._h, ctypes.byref(t)), "axf_batch_tile")
+        return t.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

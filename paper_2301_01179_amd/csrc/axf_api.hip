@@ -142,6 +142,10 @@ void plan_release(Plan *pl)
     release_events(pl);
     if (pl->tables_ready) (void)hipEventDestroy(pl->tables_ready);
     pl->tables_ready = nullptr;
+    for (hipEvent_t *e : {&pl->ev_fork, &pl->ev_join}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
     arena_release(pl->points);
     arena_release(pl->tree);
     arena_release(pl->expn);
@@ -160,6 +164,9 @@ static void validate_params(const axf_params *p)
     AXF_REQUIRE(p->depth != 0 || p->max_leaf >= 1, AXF_ERR_INVALID_ARGUMENT,
                 "max_leaf must be >= 1 when depth is 0");
     AXF_REQUIRE(p->nrhs >= 1 && p->nrhs <= AXF_MAX_RHS, AXF_ERR_UNSUPPORTED, "nrhs must be in 1..8");
+    AXF_REQUIRE((p->flags & ~AXF_TILE_MASK) == 0, AXF_ERR_INVALID_ARGUMENT, "unknown plan flags");
+    const int tb = (int)((p->flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
+    AXF_REQUIRE(tb == 0 || s2l_tile_ok(tb), AXF_ERR_UNSUPPORTED, "S2L tile width must be 2, 4 or 8 (or 0)");
 }
 
 // The stream that builds a plan's tables beside the tree (one per device,
@@ -189,6 +196,10 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     pl.TS = (p.order + 1) * (p.order + 1) * (p.order + 1);
     pl.chistar = forward_chi_limit(p.n_modes);
     pl.nmb = mode_bucket(p.n_modes);
+    {
+        const int tb = (int)((p.flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
+        pl.tb = tb ? tb : kDefaultTile;
+    }
     pl.Cs = pl.nmb * p.nrhs;
     pl.src.n = ns;
     pl.fld.n = nf;
@@ -230,6 +241,8 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
         if (!pl.tables_ready) AXF_HIP(hipEventCreateWithFlags(&pl.tables_ready, hipEventDisableTiming));
         AXF_HIP(hipEventRecord(pl.tables_ready, side));
     };
+    AXF_HIP(hipEventCreateWithFlags(&pl.ev_fork, hipEventDisableTiming));
+    AXF_HIP(hipEventCreateWithFlags(&pl.ev_join, hipEventDisableTiming));
     build_tree(pl, rs, zs, rf, zf, st, start_tables);
     build_tiles(pl, st);
 
@@ -610,7 +623,8 @@ axf_status axf_plan_work(const axf_plan *plan, int64_t *near_pairs, int64_t *s2l
             // (dr, dz) and (dr, -dz) share it
             flops[AXF_PHASE_S2L] = (double)pl.s2l_units * C * P * P * 4.0;
             flops[AXF_PHASE_L2L] = nbox_down * C * c3 * 8.0;
-            flops[AXF_PHASE_LEAF] = pair_flops(pl.census_near) + (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
+            flops[AXF_PHASE_LEAF] = pair_flops(pl.census_near);
+            flops[AXF_PHASE_L2P] = (double)pl.fld.n * (4.0 * P * C + 2.0 * P);
             flops[AXF_PHASE_DIRECT] = pair_flops(pl.census_direct);
         }
     })

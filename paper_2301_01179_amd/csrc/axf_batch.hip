@@ -7,12 +7,19 @@
 // whole batch is ~2 d_max kernel launches regardless of the number of
 // problems.  The launch sequence is captured once in a HIP graph and replayed.
 //
-// Autotuner: for every candidate depth the exact work of the FMM is counted
-// on the host from the points (near-field pairs, S2L box pairs, occupied
-// boxes), and the depth with the smallest modelled time is kept.  The model's
-// rates are the measured throughputs of the kernels on MI355X.
+// Autotuner: the rates of the evaluation's parts (seconds per near-field
+// pair, per S2L unit and channel, per shifted box and channel, per point and
+// channel) are measured on the device when a batch is created, by timing the
+// phases of a probe problem at two depths; they are kept per device, order,
+// mode count and tile width for the process.  The S2L tile width is the one
+// whose probe S2L ran fastest.  Each problem's depth is then the one whose
+// exactly counted work (near pairs, S2L units, shifted boxes, points, on the
+// square the plan will use) costs the least at those rates.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "axf_device.hpp"
@@ -27,65 +34,92 @@ void plan_release(Plan *pl);
 
 namespace {
 
-// Modelled seconds of one evaluation at depth d (work counted on the host).
-struct DepthModel {
-    double near_pair_s, s2l_flop_s, m2m_box_s, leaf_point_s;
+// Seconds per unit of work of one evaluation's parts.
+struct Rates {
+    double near_pair = 0;    // per near-field pair and right-hand side
+    double s2l_unit = 0;     // per S2L unit and channel
+    double box = 0;          // per (box, channel) of the M2M and L2L shifts
+    double point = 0;        // per (point, channel) of moments, gather and local evaluation
+    double s2l_seconds = 0;  // the probe's S2L time (ranks the tile widths)
 };
 
-DepthModel model_rates(int M, int nmodes, int nrhs)
+struct Work {
+    double near = 0, units = 0, boxes = 0;
+};
+
+// The square plan_build will use (the same rule as the tree builder): side =
+// larger extent; in r it starts on the axis when that side reaches the
+// largest radius, else at the smallest radius; in z at the smallest z.
+struct Square {
+    double rlo = 0, zlo = 0, invL = 1;
+};
+Square plan_square(const std::vector<double> &rs, const std::vector<double> &zs, const std::vector<double> &rf,
+                   const std::vector<double> &zf)
 {
-    DepthModel m;
-    // near field: 6.6e-11 s per pair at 17 modes, one right-hand side; the
-    // kernel re-evaluates G for every right-hand side
-    m.near_pair_s = 6.6e-11 * (nmodes + 17.0) / 34.0 * nrhs;
-    // tiled S2L: ~3 TFLOP/s at M = 12 rising to ~7 TFLOP/s at M = 24
-    double rate = 3e12 + std::max(0, std::min(12, M - 12)) * (4e12 / 12.0);
-    m.s2l_flop_s = 1.0 / rate;
-    const double c4 = (M + 1.0) * (M + 2) * (M + 3) * (M + 4) / 24.0;
-    m.m2m_box_s = 4.6e-11 * c4 * nmodes * nrhs;
-    const double P = (M + 1.0) * (M + 2) / 2;
-    m.leaf_point_s = 2e-12 * P * nmodes * nrhs;
-    return m;
+    double rmin = INFINITY, rmax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+    for (auto v : {&rs, &rf})
+        for (double x : *v) {
+            rmin = std::min(rmin, x);
+            rmax = std::max(rmax, x);
+        }
+    for (auto v : {&zs, &zf})
+        for (double x : *v) {
+            zmin = std::min(zmin, x);
+            zmax = std::max(zmax, x);
+        }
+    const double ext = std::max(rmax - rmin, zmax - zmin);
+    Square q;
+    q.rlo = rmax <= ext ? 0.0 : rmin;
+    q.zlo = zmin;
+    q.invL = 1.0 / (ext > 0.0 ? ext : 1.0);
+    return q;
 }
 
-struct Counts {
-    double near = 0, s2l = 0, boxes = 0;
-};
-
-// Work of the uniform tree at depth d over the union bounding square.
-Counts count_work(const std::vector<double> &rs, const std::vector<double> &zs, const std::vector<double> &rf,
-                  const std::vector<double> &zf, double rlo, double zlo, double invL, int d)
+// Exact work of the uniform tree at depth d: near-field pairs over the 3x3
+// neighbour leaves, S2L units (a target box with the source boxes at (dr, dz)
+// and (dr, -dz) of its interaction list, either occupied: the pairing of the
+// tiled S2L), and the boxes the M2M (source parents) and L2L (target
+// children) shift.
+Work count_work(const std::vector<double> &rs, const std::vector<double> &zs, const std::vector<double> &rf,
+                const std::vector<double> &zf, const Square &sq, int d)
 {
     const int nb = 1 << d;
     std::vector<int32_t> cs((size_t)nb * nb, 0), cf((size_t)nb * nb, 0);
     for (size_t i = 0; i < rs.size(); ++i)
-        cs[(size_t)box_index(rs[i], rlo, invL, d) * nb + box_index(zs[i], zlo, invL, d)]++;
+        cs[(size_t)box_index(rs[i], sq.rlo, sq.invL, d) * nb + box_index(zs[i], sq.zlo, sq.invL, d)]++;
     for (size_t i = 0; i < rf.size(); ++i)
-        cf[(size_t)box_index(rf[i], rlo, invL, d) * nb + box_index(zf[i], zlo, invL, d)]++;
-    Counts c;
+        cf[(size_t)box_index(rf[i], sq.rlo, sq.invL, d) * nb + box_index(zf[i], sq.zlo, sq.invL, d)]++;
+    Work w;
     for (int ir = 0; ir < nb; ++ir)
         for (int iz = 0; iz < nb; ++iz) {
-            int t = cf[(size_t)ir * nb + iz];
+            const int t = cf[(size_t)ir * nb + iz];
             if (!t) continue;
             long long s = 0;
             for (int jr = std::max(ir - 1, 0); jr <= std::min(ir + 1, nb - 1); ++jr)
                 for (int jz = std::max(iz - 1, 0); jz <= std::min(iz + 1, nb - 1); ++jz) s += cs[(size_t)jr * nb + jz];
-            c.near += (double)t * s;
+            w.near += (double)t * s;
         }
-    // coarser levels by aggregation
     std::vector<int32_t> s_l = cs, f_l = cf;
     for (int l = d; l >= 2; --l) {
         const int n = 1 << l;
         for (int ir = 0; ir < n; ++ir)
             for (int iz = 0; iz < n; ++iz) {
+                if (l < d && s_l[(size_t)ir * n + iz]) w.boxes += 1;        // M2M parent
                 if (!f_l[(size_t)ir * n + iz]) continue;
-                c.boxes += 1;
-                for (int jr = 2 * (ir >> 1) - 2; jr < 2 * (ir >> 1) + 4; ++jr)
-                    for (int jz = 2 * (iz >> 1) - 2; jz < 2 * (iz >> 1) + 4; ++jz) {
-                        if (jr < 0 || jz < 0 || jr >= n || jz >= n) continue;
-                        if (std::abs(jr - ir) <= 1 && std::abs(jz - iz) <= 1) continue;
-                        if (s_l[(size_t)jr * n + jz]) c.s2l += 1;
+                if (l > 2) w.boxes += 1;                                     // L2L child
+                const int dr0 = -2 - (ir & 1), dz0 = -2 - (iz & 1);
+                for (int dr = dr0; dr < dr0 + 6; ++dr) {
+                    const int jr = ir + dr;
+                    if (jr < 0 || jr >= n) continue;
+                    const bool near_r = dr >= -1 && dr <= 1;
+                    for (int adz = 0; adz <= 3; ++adz) {
+                        const bool hasp = adz > 0 && adz <= dz0 + 5 && !(near_r && adz <= 1);
+                        const bool hasm = -adz >= dz0 && !(near_r && adz <= 1);
+                        const bool occp = hasp && iz + adz < n && s_l[(size_t)jr * n + iz + adz];
+                        const bool occm = hasm && iz - adz >= 0 && s_l[(size_t)jr * n + iz - adz];
+                        if (occp || occm) w.units += 1;
                     }
+                }
             }
         if (l == 2) break;
         const int h = n / 2;
@@ -98,10 +132,113 @@ Counts count_work(const std::vector<double> &rs, const std::vector<double> &zs, 
         s_l.swap(s2);
         f_l.swap(f2);
     }
-    return c;
+    return w;
 }
 
-int autotune_depth(const axf_problem &pb, int M, int nmodes, hipStream_t st)
+// Phase times of the plan's recorded marks (milliseconds per phase).
+void read_marks(Plan &pl, double ms[AXF_NUM_PHASES])
+{
+    for (int i = 0; i < AXF_NUM_PHASES; ++i) ms[i] = 0.0;
+    for (auto &m : pl.marks) {
+        AXF_HIP(hipEventSynchronize(m.b));
+        float t = 0.f;
+        AXF_HIP(hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.phase] += t;
+    }
+}
+
+// Rates from a probe: 20,000 rings of the ring box [0.5, 1.5] x [-0.5, 0.5]
+// (a two-dimensional additive recurrence, no random numbers), sources =
+// field points, one right-hand side, unit strengths, at depths 4 and 5; the
+// leaf runs fused with the local evaluation, as in the batch kernels.
+Rates probe_rates(int M, int nmodes, int tb, hipStream_t st)
+{
+    const int n = 20000;
+    std::vector<double> h(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const double a = (i + 0.5) * 0.7548776662466927, b = (i + 0.5) * 0.5698402909980532;
+        h[i] = 0.5 + (a - std::floor(a));
+        h[n + i] = -0.5 + (b - std::floor(b));
+    }
+    Sizer sz;
+    sz.add<double>(2 * (size_t)n);
+    sz.add<double2>((size_t)nmodes * n);
+    sz.add<double2>((size_t)nmodes * n);
+    Arena a = arena_acquire(sz.bytes + 4096);
+    double *xy = a.take<double>(2 * (size_t)n);
+    double2 *S = a.take<double2>((size_t)nmodes * n);
+    double2 *phi = a.take<double2>((size_t)nmodes * n);
+    std::vector<double2> ones((size_t)nmodes * n, make_double2(1.0, 0.0));
+    Rates r;
+    double ms[AXF_NUM_PHASES] = {}, near = 0, units = 0, boxes = 0, pts = 0;
+    try {
+        AXF_HIP(hipMemcpyAsync(xy, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        AXF_HIP(hipMemcpyAsync(S, ones.data(), ones.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        for (int d : {4, 5}) {
+            axf_params pp{};
+            pp.n_modes = nmodes;
+            pp.order = M;
+            pp.depth = d;
+            pp.max_leaf = 64;
+            pp.nrhs = 1;
+            pp.flags = AXF_TILE(tb);
+            Plan pl;
+            try {
+                plan_build(pl, pp, n, xy, xy + n, n, xy, xy + n, st);
+                if (pl.tables_ready) AXF_HIP(hipEventSynchronize(pl.tables_ready));
+                EvalOut o;
+                o.phi = (double *)phi;
+                o.fused = true;
+                run_fmm(pl, pl.src, pl.fld, (const double *)S, o, st);
+                pl.timing = true;
+                for (int rep = 0; rep < 2; ++rep) run_fmm(pl, pl.src, pl.fld, (const double *)S, o, st);
+                double m[AXF_NUM_PHASES];
+                read_marks(pl, m);
+                for (int i = 0; i < AXF_NUM_PHASES; ++i) ms[i] += m[i] / 2.0;
+                near += pl.near_pairs;
+                units += (double)pl.s2l_units * pl.C;
+                for (int l = 2; l < pl.d; ++l) boxes += (double)pl.src.nocc[l] * pl.C;
+                for (int l = 3; l <= pl.d; ++l) boxes += (double)pl.fld.nocc[l] * pl.C;
+                pts += 2.0 * n * pl.C;
+            } catch (...) {
+                plan_release(&pl);
+                throw;
+            }
+            plan_release(&pl);
+        }
+    } catch (...) {
+        arena_release(a);
+        throw;
+    }
+    arena_release(a);
+    r.near_pair = ms[AXF_PHASE_LEAF] * 1e-3 / std::max(near, 1.0);
+    r.s2l_unit = ms[AXF_PHASE_S2L] * 1e-3 / std::max(units, 1.0);
+    r.box = (ms[AXF_PHASE_M2M] + ms[AXF_PHASE_L2L]) * 1e-3 / std::max(boxes, 1.0);
+    r.point = (ms[AXF_PHASE_GATHER] + ms[AXF_PHASE_P2M]) * 1e-3 / std::max(pts, 1.0);
+    r.s2l_seconds = ms[AXF_PHASE_S2L] * 1e-3;
+    return r;
+}
+
+Rates measured_rates(int M, int nmodes, int tb, hipStream_t st)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, Rates> cache;
+    int dev = 0;
+    AXF_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, M, nmodes, tb);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    Rates r = probe_rates(M, nmodes, tb, st);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = r;
+    return r;
+}
+
+// The depth of least modelled time for one problem.
+int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_t st)
 {
     std::vector<double> rs(pb.ns), zs(pb.ns), rf(pb.nf), zf(pb.nf);
     AXF_HIP(hipMemcpyAsync(rs.data(), pb.r_src, pb.ns * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -109,30 +246,16 @@ int autotune_depth(const axf_problem &pb, int M, int nmodes, hipStream_t st)
     AXF_HIP(hipMemcpyAsync(rf.data(), pb.r_fld, pb.nf * sizeof(double), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipMemcpyAsync(zf.data(), pb.z_fld, pb.nf * sizeof(double), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipStreamSynchronize(st));
-    double rmin = INFINITY, rmax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
-    for (auto v : {&rs, &rf})
-        for (double x : *v) {
-            rmin = std::min(rmin, x);
-            rmax = std::max(rmax, x);
-        }
-    for (auto v : {&zs, &zf})
-        for (double x : *v) {
-            zmin = std::min(zmin, x);
-            zmax = std::max(zmax, x);
-        }
-    double ext = std::max(rmax - rmin, zmax - zmin);
-    double L = ext > 0 ? ext : 1.0, invL = 1.0 / L;
-    DepthModel m = model_rates(M, nmodes, pb.nrhs);
-    const double P = (M + 1.0) * (M + 2) / 2;
+    const Square sq = plan_square(rs, zs, rf, zf);
     const double C = (double)nmodes * pb.nrhs;
     int best = 2;
     double best_t = INFINITY;
     const double npts = (double)std::max(pb.ns, pb.nf);
     for (int d = 2; d <= AXF_MAX_DEPTH; ++d) {
         if (d > 2 && npts / std::pow(4.0, d - 1) < 1.0) break;   // deeper than one point per box
-        Counts c = count_work(rs, zs, rf, zf, rmin, zmin, invL, d);
-        double t = c.near * m.near_pair_s + c.s2l * C * P * P * 4.0 * m.s2l_flop_s + c.boxes * m.m2m_box_s +
-                   (double)pb.nf * m.leaf_point_s + 5e-6 * d;
+        const Work w = count_work(rs, zs, rf, zf, sq, d);
+        const double t = w.near * pb.nrhs * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
+                         (double)(pb.ns + pb.nf) * C * r.point;
         if (t < best_t) {
             best_t = t;
             best = d;
@@ -152,6 +275,7 @@ struct axf_batch {
     std::vector<axf_problem> probs;
     std::vector<Plan *> plans;
     std::vector<int> depth;
+    int tb = kDefaultTile;
     Arena qmem;
     BatchQueues q;
     hipGraph_t graph = nullptr;
@@ -199,23 +323,47 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             AXF_REQUIRE(pb.depth != 0 || !(params->flags & AXF_BATCH_NO_AUTOTUNE) || params->max_leaf >= 1,
                         AXF_ERR_INVALID_ARGUMENT, "max_leaf must be >= 1 without the autotuner");
         }
+        AXF_REQUIRE((params->flags & ~(AXF_BATCH_NO_AUTOTUNE | AXF_TILE_MASK)) == 0, AXF_ERR_INVALID_ARGUMENT,
+                    "unknown batch flags");
+        const int tb_given = (int)((params->flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
+        AXF_REQUIRE(tb_given == 0 || s2l_tile_ok(tb_given), AXF_ERR_UNSUPPORTED,
+                    "S2L tile width must be 2, 4 or 8 (or 0)");
         hipStream_t st = (hipStream_t)stream;
         b = new axf_batch();
         AXF_HIP(hipGetDevice(&b->device));
         b->p = *params;
         b->probs.assign(problems, problems + nprob);
+        const bool tune = !(params->flags & AXF_BATCH_NO_AUTOTUNE);
+        // tile width: given, or the one whose probe S2L ran fastest
+        Rates rates;
+        if (tb_given) {
+            b->tb = tb_given;
+        } else if (!tune) {
+            b->tb = kDefaultTile;
+        } else {
+            double best = INFINITY;
+            for (int tb : {2, 4, 8}) {
+                Rates r = measured_rates(params->order, params->n_modes, tb, st);
+                if (r.s2l_seconds < best) {
+                    best = r.s2l_seconds;
+                    b->tb = tb;
+                    rates = r;
+                }
+            }
+        }
+        if (tune && tb_given) rates = measured_rates(params->order, params->n_modes, b->tb, st);
         int maxd = 2;
         for (int i = 0; i < nprob; ++i) {
             const axf_problem &pb = problems[i];
             axf_params pp = *params;
             pp.nrhs = pb.nrhs;
-            pp.flags = 0;
+            pp.flags = AXF_TILE(b->tb);
             if (pb.depth != 0) {
                 pp.depth = pb.depth;
             } else if (params->flags & AXF_BATCH_NO_AUTOTUNE) {
                 pp.depth = 0;
             } else {
-                pp.depth = autotune_depth(pb, params->order, params->n_modes, st);
+                pp.depth = autotune_depth(pb, params->n_modes, rates, st);
             }
             Plan *pl = new Plan();
             b->plans.push_back(pl);
@@ -279,6 +427,7 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
         q.TS = (params->order + 1) * (params->order + 1) * (params->order + 1);
         q.maxd = maxd;
         q.chistar = b->plans[0]->chistar;
+        q.tb = b->tb;
         // one eager pass (sets kernel attributes), then capture the sequence
         run_batch(q, st);
         AXF_HIP(hipStreamSynchronize(st));
@@ -337,6 +486,17 @@ axf_status axf_batch_problem_depth(const axf_batch *b, int32_t i, int32_t *depth
         AXF_REQUIRE(b && depth && i >= 0 && i < (int32_t)b->depth.size(), AXF_ERR_INVALID_ARGUMENT,
                     "bad batch, index or output pointer");
         *depth = b->depth[i];
+        return AXF_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+}
+
+axf_status axf_batch_tile(const axf_batch *b, int32_t *tile)
+{
+    try {
+        AXF_REQUIRE(b && tile, AXF_ERR_INVALID_ARGUMENT, "batch and tile must be non-NULL");
+        *tile = b->tb;
         return AXF_OK;
     } catch (const Fail &f) {
         return f.st;

@@ -11,7 +11,10 @@
 //   table at r >= r1, x >= 0 serves all four orientations.
 #include <algorithm>
 
+#include <mutex>
+
 #include "axf_device.hpp"
+
 #include "axf_internal.hpp"
 
 namespace axf {
@@ -858,8 +861,10 @@ constexpr size_t leaf_lds_bytes()
 // expansion (eq. analysis:local) plus the direct sum over the 3x3 neighbour
 // leaves, the sources dealt round-robin to the four waves.
 // MODE 0: potential; 1: potential and gradient; 2: potential and the
-// adjoint coordinate contraction.
-template <int NMB, int MODE>
+// adjoint coordinate contraction.  PART 0: both sums; PART 1 (MODE 0): the
+// near field only, written to phi (it needs no local expansions, so it runs
+// beside the downward pass; k_l2p adds them afterwards).
+template <int NMB, int MODE, int PART = 0>
 __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth, double rlo, double zlo,
                                              double invh, double chistar, const int4 *__restrict__ chunks,
                                              SideView tv, SideView sv, const double *__restrict__ sinv,
@@ -895,7 +900,7 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
         A.zero();
         // local expansion, monomials dealt round-robin over the waves
         const double2 *lc = loc + (int64_t)ch.x * C * P;
-        {
+        if constexpr (PART != 1) {
             double pr = 1.0, pr1 = 0.0;
             int p = 0;
             for (int kk = 0; kk <= M; ++kk) {
@@ -994,7 +999,7 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
     }
 }
 
-template <int NMB, int MODE>
+template <int NMB, int MODE, int PART>
 __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
     int M, int nmodes, int nrhs, int depth, double rlo, double zlo, double invh, double chistar,
     const int4 *__restrict__ chunks, SideView tv, SideView sv, const double *__restrict__ sinv,
@@ -1003,8 +1008,54 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
     const double2 *__restrict__ Sdot,
     double *__restrict__ gr, double *__restrict__ gz, int64_t ntot, int Cs)
 {
-    leaf_body<NMB, MODE>(M, nmodes, nrhs, depth, rlo, zlo, invh, chistar, chunks, tv, sv, sinv, Sg, loc, phi, dphr,
-                         dphz, dpha, Sdot, gr, gz, ntot, Cs, blockIdx.x);
+    leaf_body<NMB, MODE, PART>(M, nmodes, nrhs, depth, rlo, zlo, invh, chistar, chunks, tv, sv, sinv, Sg, loc, phi,
+                               dphr, dphz, dpha, Sdot, gr, gz, ntot, Cs, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ L2P
+// Local expansions at the field points (eq. analysis:local), added to the
+// near field already in phi: one block per (chunk of <= 64 targets, group of
+// kL2PChannels channels); the chunk's leaf coefficients of those channels
+// are staged in LDS and each wave evaluates one channel at its targets by
+// Horner's rule in z nested in Horner's rule in r (offsets in box units).
+constexpr int kL2PChannels = 4;
+__global__ __launch_bounds__(64 * kL2PChannels) void k_l2p(int M, int nmodes, int nrhs, int depth, double rlo,
+                                                           double zlo, double invh, const int4 *__restrict__ chunks,
+                                                           SideView tv, const double2 *__restrict__ loc,
+                                                           double2 *__restrict__ phi, int64_t ntot)
+{
+    extern __shared__ double2 cf[];          // [kL2PChannels][P]
+    const int P = (M + 1) * (M + 2) / 2, C = nmodes * nrhs;
+    const int ngrp = (C + kL2PChannels - 1) / kL2PChannels;
+    const int ci = blockIdx.x / ngrp, grp = blockIdx.x - ci * ngrp;
+    const int4 ch = chunks[ci];
+    const int c0 = grp * kL2PChannels, nc = min(kL2PChannels, C - c0);
+    const double2 *lc = loc + ((int64_t)ch.x * C + c0) * P;
+    for (int e = threadIdx.x; e < nc * P; e += blockDim.x) cf[e] = lc[e];
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (w >= nc || lane >= ch.z) return;
+    const int c = c0 + w, n = c / nrhs, q = c - n * nrhs;
+    const int nb = 1 << depth;
+    const int ir = ch.w / nb, iz = ch.w - (ch.w / nb) * nb;
+    const int t = ch.y + lane;
+    const double xr = (tv.r[t] - rlo) * invh - (ir + 0.5);
+    const double xz = (tv.z[t] - zlo) * invh - (iz + 0.5);
+    const double2 *ck = cf + w * P;
+    double ar = 0.0, ai = 0.0;
+    for (int kk = M; kk >= 0; --kk) {
+        const int base = kk * (M + 1) - (kk * (kk - 1)) / 2;     // packed (kk, 0)
+        double sr = ck[base + M - kk].x, si = ck[base + M - kk].y;
+        for (int ll = M - kk - 1; ll >= 0; --ll) {
+            sr = fma(sr, xz, ck[base + ll].x);
+            si = fma(si, xz, ck[base + ll].y);
+        }
+        ar = fma(ar, xr, sr);
+        ai = fma(ai, xr, si);
+    }
+    const int64_t o = ((int64_t)q * nmodes + n) * ntot + tv.perm[t];
+    const double2 v = phi[o];
+    phi[o] = make_double2(v.x + ar, v.y + ai);
 }
 
 // ---------------------------------------------------------------- direct
@@ -1071,10 +1122,23 @@ SideView view_of(const Side &s)
     return v;
 }
 
+// Dynamic LDS above 64 KiB (wide tiles at high order) needs the kernel's
+// attribute raised once per device.
+template <class K>
+void allow_lds(K kernel, size_t shm, int device, bool (&done)[64])
+{
+    if (shm > 65536 && !done[device & 63]) {
+        AXF_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        done[device & 63] = true;
+    }
+}
+
 template <int LB, int TB, int MW, bool FIX>
 void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     size_t shm = sizeof(double2) * 2 * (size_t)TB * pl.P;
+    static bool attr[64] = {};
+    allow_lds(k_s2l_tile<LB, TB, MW, FIX>, shm, pl.device, attr);
     const int G = tgt.s2l_groups[l];
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
     k_s2l_tile<LB, TB, MW, FIX><<<tgt.ntiles[l] * pl.C * G, 64 * s2l_waves(pl.M), shm, st>>>(
@@ -1095,12 +1159,18 @@ void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t s
                                                    l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc, pl.shift_coef);
     }
     PhaseTimer tm(pl, st, AXF_PHASE_S2L);
-#define AXF_S2L_LAUNCH(LB, MW, FIX) launch_s2l_t<LB, 4, MW, FIX>(pl, src, tgt, l, st)
-    AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH);
-#undef AXF_S2L_LAUNCH
+#define AXF_S2L_LAUNCH2(LB, MW, FIX) launch_s2l_t<LB, 2, MW, FIX>(pl, src, tgt, l, st)
+#define AXF_S2L_LAUNCH4(LB, MW, FIX) launch_s2l_t<LB, 4, MW, FIX>(pl, src, tgt, l, st)
+#define AXF_S2L_LAUNCH8(LB, MW, FIX) launch_s2l_t<LB, 8, MW, FIX>(pl, src, tgt, l, st)
+    if (pl.tb == 2) AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH2);
+    else if (pl.tb == 8) AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH8);
+    else AXF_S2L_SHAPES(pl.M, AXF_S2L_LAUNCH4);
+#undef AXF_S2L_LAUNCH2
+#undef AXF_S2L_LAUNCH4
+#undef AXF_S2L_LAUNCH8
 }
 
-template <int NMB, int MODE>
+template <int NMB, int MODE, int PART = 0>
 void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
 {
     SideView tv = view_of(tgt), sv = view_of(src);
@@ -1109,12 +1179,12 @@ void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut 
     constexpr size_t shm = leaf_lds_bytes<NMB, MODE>();
     static bool attr[64] = {};
     if (shm > 65536 && !attr[pl.device & 63]) {
-        AXF_HIP(hipFuncSetAttribute((const void *)k_leaf<NMB, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        AXF_HIP(hipFuncSetAttribute((const void *)k_leaf<NMB, MODE, PART>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));
         attr[pl.device & 63] = true;
     }
     if (tgt.nchunks == 0) return;
-    k_leaf<NMB, MODE><<<tgt.nchunks, 64 * PairShape<NMB>::WPB, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
+    k_leaf<NMB, MODE, PART><<<tgt.nchunks, 64 * PairShape<NMB>::WPB, shm, st>>>(pl.M, pl.nmodes, pl.nrhs, pl.d, pl.rlo, pl.zlo, invh,
                                                      pl.chistar, tgt.chunks, tv, sv, src.rinv, pl.Sg, loc,
                                                      (double2 *)out.phi, (double2 *)out.dr, (double2 *)out.dz,
                                                      (double2 *)out.daz, (const double2 *)out.Sdot, out.gr, out.gz, tgt.n,
@@ -1122,9 +1192,10 @@ void launch_leaf_mode(Plan &pl, const Side &src, const Side &tgt, const EvalOut 
 }
 
 template <int NMB>
-void launch_leaf(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
+void launch_leaf(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st, int part = 0)
 {
-    if (out.mode == 0) launch_leaf_mode<NMB, 0>(pl, src, tgt, out, st);
+    if (out.mode == 0 && part == 1) launch_leaf_mode<NMB, 0, 1>(pl, src, tgt, out, st);
+    else if (out.mode == 0) launch_leaf_mode<NMB, 0>(pl, src, tgt, out, st);
     else if (out.mode == 1) launch_leaf_mode<NMB, 1>(pl, src, tgt, out, st);
     else launch_leaf_mode<NMB, 2>(pl, src, tgt, out, st);
 }
@@ -1248,6 +1319,10 @@ void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
 {
     const int P = (bq.M + 1) * (bq.M + 2) / 2;
     size_t shm = sizeof(double2) * 2 * (size_t)TB * P;
+    static bool attr[64] = {};
+    int dev = 0;
+    AXF_HIP(hipGetDevice(&dev));
+    allow_lds(kb_s2l<LB, TB, MW, FIX>, shm, dev, attr);
     int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
     kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }
@@ -1388,6 +1463,18 @@ void shift_coef_host(int M, std::vector<double> &out)
     }
 }
 
+// The stream on which the near field of an evaluation runs beside the
+// downward pass (one per device, default priority, kept for the process).
+static hipStream_t near_stream(int device)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    hipStream_t &s = streams[device & 63];
+    if (!s) AXF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+}
+
 void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out, hipStream_t st)
 {
     const int M = pl.M, P = pl.P, C = pl.C, d = pl.d;
@@ -1398,6 +1485,12 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
         k_gather<<<(int)((tot + 255) / 256), 256, 0, st>>>((const double2 *)S, src.perm, ns, pl.nmodes, pl.nrhs,
                                                           pl.Cs, pl.Sg);
     }
+    // potential only: the near field needs only the gathered strengths, so it
+    // runs on a second stream beside the downward pass (both are
+    // latency-bound and leave issue slots to the other); it is started after
+    // the short upward pass so that it does not hold the CUs that pass
+    // needs; the local expansions are added once both are done
+    const bool split = out.mode == 0 && !out.fused && tgt.nchunks > 0;
     SideView sv = view_of(src);
     if (src.nocc[d] > 0) {
         PhaseTimer tm(pl, st, AXF_PHASE_P2M);
@@ -1411,6 +1504,19 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
                 k_m2m<<<src.nocc[l] * C, 256, 0, st>>>(M, C, l, src.box[l], src.slot[l + 1], pl.lev[l + 1].mom,
                                                    pl.lev[l].mom, pl.shift_coef);
     }
+    if (split) {
+        hipStream_t side = near_stream(pl.device);
+        AXF_HIP(hipEventRecord(pl.ev_fork, st));
+        AXF_HIP(hipStreamWaitEvent(side, pl.ev_fork, 0));
+        {
+            PhaseTimer tm(pl, side, AXF_PHASE_LEAF);
+#define AXF_NEAR(B) \
+    if (pl.nmb == B) launch_leaf<B>(pl, src, tgt, out, side, 1);
+            AXF_BUCKETS(AXF_NEAR)
+#undef AXF_NEAR
+        }
+        AXF_HIP(hipEventRecord(pl.ev_join, side));
+    }
     {
         // the tables (built on the table stream) are needed from here on
         if (pl.tables_ready) AXF_HIP(hipStreamWaitEvent(st, pl.tables_ready, 0));
@@ -1420,6 +1526,16 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
         }
     }
     (void)pl.nmodes;
+    if (split) {
+        AXF_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
+        PhaseTimer tm(pl, st, AXF_PHASE_L2P);
+        const int ngrp = (C + kL2PChannels - 1) / kL2PChannels;
+        k_l2p<<<tgt.nchunks * ngrp, 64 * kL2PChannels, sizeof(double2) * kL2PChannels * P, st>>>(
+            M, pl.nmodes, pl.nrhs, d, pl.rlo, pl.zlo, (double)(1 << d) * pl.invL, tgt.chunks, view_of(tgt),
+            pl.lev[d].loc, (double2 *)out.phi, tgt.n);
+        AXF_HIP(hipGetLastError());
+        return;
+    }
     PhaseTimer tm_leaf(pl, st, AXF_PHASE_LEAF);
 #define AXF_LEAF(B)                                         \
     if (pl.nmb == B) {                                      \
@@ -1465,9 +1581,15 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
         if (bq.nl2l[l])
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
         if (!bq.ns2l[l]) continue;
-#define AXF_S2L_LAUNCH(LB, MW, FIX) launch_s2l_batch<LB, 4, MW, FIX>(bq, l, st)
-        AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH);
-#undef AXF_S2L_LAUNCH
+#define AXF_S2L_LAUNCH2(LB, MW, FIX) launch_s2l_batch<LB, 2, MW, FIX>(bq, l, st)
+#define AXF_S2L_LAUNCH4(LB, MW, FIX) launch_s2l_batch<LB, 4, MW, FIX>(bq, l, st)
+#define AXF_S2L_LAUNCH8(LB, MW, FIX) launch_s2l_batch<LB, 8, MW, FIX>(bq, l, st)
+        if (bq.tb == 2) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH2);
+        else if (bq.tb == 8) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH8);
+        else AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH4);
+#undef AXF_S2L_LAUNCH2
+#undef AXF_S2L_LAUNCH4
+#undef AXF_S2L_LAUNCH8
     }
     if (bq.nleaf) {
 #define AXF_LEAFB(B)                          \

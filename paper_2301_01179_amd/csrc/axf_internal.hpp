@@ -115,7 +115,10 @@ inline int s2l_slots(int M, int lb)
 }
 inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
-inline int s2l_tb(int) { return 4; }
+// Tile widths the S2L kernels are compiled for (boxes per tile); a plan's
+// comes from params.flags (AXF_TILE_SHIFT), 0 meaning kDefaultTile.
+constexpr int kDefaultTile = 4;
+inline bool s2l_tile_ok(int tb) { return tb == 2 || tb == 4 || tb == 8; }
 // P2M work items per leaf: one per pair of channels (the pair shares the
 // sources' offset powers).
 __host__ __device__ inline int p2m_pairs(int C) { return (C + 1) / 2; }
@@ -159,6 +162,7 @@ struct Plan {
     axf_params p{};
     int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
     int nmb = 4, Cs = 4;        // mode bucket and padded channels per point in Sg
+    int tb = kDefaultTile;      // S2L tile width (target boxes per tile)
     double rlo = 0, zlo = 0, L = 1, invL = 1;
     double rmax = 0;                     // largest ring radius of both sets
     int tab_smax[AXF_MAX_DEPTH + 1] = {};   // last radial station with tables, per level
@@ -173,6 +177,7 @@ struct Plan {
     Arena points, tree, expn, tilemem, tabmem;
     std::vector<double> geom_host;   // table geometries (4 doubles each), source of an async copy
     hipEvent_t tables_ready = nullptr;   // recorded after the tables on the table stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // near field beside the downward pass
     double *shift_coef = nullptr;        // M2M and L2L factors, [3][2][S][S], S = AXF_MAX_ORDER + 1
     std::vector<double> coef_host;       // their host copy, source of an async copy
     std::vector<int32_t> box_host;       // every level's occupied boxes of both sides (host copy)
@@ -272,6 +277,7 @@ struct EvalOut {
     const double *Sdot = nullptr;  // mode 2: caller-order strengths at the targets
     double *gr = nullptr, *gz = nullptr;
     int mode = 0;
+    bool fused = false;          // mode 0: near field and local evaluation in one kernel
 };
 void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const EvalOut &out,
              hipStream_t st);
@@ -311,7 +317,7 @@ struct BatchQueues {
     int ngather = 0, np2m = 0, nleaf = 0;
     int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *s2l[AXF_MAX_DEPTH + 1] = {}, *l2l[AXF_MAX_DEPTH + 1] = {};
     int nm2m[AXF_MAX_DEPTH + 1] = {}, ns2l[AXF_MAX_DEPTH + 1] = {}, nl2l[AXF_MAX_DEPTH + 1] = {};
-    int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2;
+    int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2, tb = kDefaultTile;
     double chistar = 1e300;
 };
 void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd);

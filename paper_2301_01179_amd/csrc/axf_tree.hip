@@ -767,7 +767,7 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
 // tile, for both sides (the adjoint uses the sources as targets).
 void build_tiles(Plan &pl, hipStream_t st)
 {
-    const int TB = s2l_tb(pl.M);
+    const int TB = pl.tb;
     Side *sides[2] = {&pl.src, &pl.fld};
     constexpr int NL = AXF_MAX_DEPTH + 1;
     // every level's box list of both sides, copied back with the tree counts

@@ -136,3 +136,4 @@ def test_batch_rejects_bad_arguments():
         axf.Batch([(r, z, r, z, S, 15)], 3, 4)       # depth beyond the maximum
     with pytest.raises(axf.AxfError):
         axf.Batch([(r, z, r, z, S)], 3, 30)          # order beyond the maximum
+

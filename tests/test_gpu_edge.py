@@ -38,10 +38,10 @@ def test_invalid_geometry(bad):
     assert ei.value.status == 2
 
 
-def _check(r, z, rf, zf, S, M, depth, tol=TOL):
+def _check(r, z, rf, zf, S, M, depth, tol=TOL, tile=0):
     axf = _axf()
     nrhs, nm, _ = S.shape
-    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs)
+    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs, tile=tile)
     d = plan.info()["depth"]
     phi = to_np(plan.evaluate(torch.from_numpy(S)))
     ref = O.fmm(r, z, rf, zf, S, M, d)
@@ -100,6 +100,17 @@ def test_s2l_orders(M):
     need_gpu()
     r, z, S = inputs.ring_box(400, 3, nrhs=2, seed=170 + M)
     _check(r, z, r, z, S, M, 3)
+
+
+@gpu
+@pytest.mark.parametrize("tile", [2, 8])
+@pytest.mark.parametrize("M", [7, 12, 22, 24])
+def test_tile_widths(tile, M):
+    """S2L tiles of 2 and 8 target boxes (the default is 4), on shapes with
+    partial rows (7, 22) and exact rows (12, 24)."""
+    need_gpu()
+    r, z, S = inputs.ring_box(900, 3, nrhs=2, seed=400 + M + tile)
+    _check(r, z, r, z, S, M, 4, tile=tile)
 
 
 @gpu
