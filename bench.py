@@ -437,6 +437,32 @@ def main():
                 "avg_launch_ms": round(ms_dom / max(launches, 1), 4),
                 "launches_per_step": launches // max(args.steps, 1)}
 
+    # the kernels on their own: the same plan with the near field after the
+    # downward pass on one stream (AXF_NO_OVERLAP), so that each kernel's
+    # launch time is not shared with the other's
+    ser = axf.Plan(rs, zs, rf, zf, nm, args.order, depth=depth, tile=tile, overlap=False)
+    ser.evaluate(S)
+    torch.cuda.synchronize()
+    ser.set_timing(True)
+    for _ in range(args.steps):
+        ser.evaluate(S)
+    torch.cuda.synchronize()
+    t_ser = ser.read_timing()
+    ser.set_timing(False)
+    ser.close()
+    standalone = {}
+    for ph in ("s2l", "leaf"):
+        ms_ph, n_ph = t_ser[ph]
+        if ms_ph > 0:
+            a = flops[ph] / (ms_ph / 1e3 / args.steps) / 1e12
+            standalone[ph] = {"achieved": round(a, 3), "frac": round(a / PEAK_FP64_VALU_TFLOPS, 4),
+                              "avg_launch_ms": round(ms_ph / max(n_ph, 1), 4),
+                              "ms_per_eval": round(ms_ph / args.steps, 4)}
+    roofline["standalone"] = standalone
+    roofline["note"] = ("achieved/frac/avg_launch_ms are from the timed (headline) evaluations, where the "
+                        "near field runs beside the S2L passes on a second stream; 'standalone' times the "
+                        "same kernels with the near field after the downward pass on one stream")
+
     secondary = None
     if not args.no_secondary and args.order != CONFIG_ORDER:
         d2, tb2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7], (2, 4, 8))

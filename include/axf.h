@@ -74,10 +74,14 @@ typedef enum {
  *   flags   : AXF_TILE(tb) selects the S2L tile width, the number of
  *             same-parity target boxes of one radial station that share one
  *             table read (section 2.2's operator reuse): 2, 4 or 8; 0 (no
- *             flag) = 4.  Other bits must be 0. */
+ *             flag) = 4.  AXF_NO_OVERLAP: potential evaluations run the near
+ *             field after the downward pass on the caller's stream instead
+ *             of beside it on a second stream of the library.  Other bits
+ *             must be 0. */
 #define AXF_TILE_SHIFT 8
 #define AXF_TILE_MASK (0xFu << AXF_TILE_SHIFT)
 #define AXF_TILE(tb) ((uint32_t)(tb) << AXF_TILE_SHIFT)
+#define AXF_NO_OVERLAP (1u << 12)
 
 typedef struct {
     int32_t n_modes;
@@ -288,9 +292,13 @@ typedef struct axf_batch axf_batch;
  * given order, mode count and tile width), takes the S2L tile width whose
  * probe ran fastest unless params->flags holds AXF_TILE(tb) (one width for
  * the whole batch), and gives every problem of depth 0 the depth of least
- * modelled time over its exactly counted work.  The problem array is host
- * memory and is copied; the S and phi buffers it names must stay valid for
- * every launch.  Synchronises `stream`. */
+ * modelled time over its exactly counted work; problems of 2,000 points or
+ * more then time trial evaluations through the batch kernels at that depth
+ * and its neighbours (continuing in the direction that improves) and keep
+ * the fastest.  Those trials read S and overwrite phi.  The problem array is
+ * host memory and is copied; the S and phi buffers it names must stay valid
+ * for every launch.  The graph runs the near field of all problems on a
+ * branch beside the downward pass.  Synchronises `stream`. */
 #define AXF_BATCH_NO_AUTOTUNE 1u
 axf_status axf_batch_create(const axf_params *params, int32_t nprob,
                             const axf_problem *problems, void *stream,

@@ -237,9 +237,13 @@ Rates measured_rates(int M, int nmodes, int tb, hipStream_t st)
     return r;
 }
 
-// The depth of least modelled time for one problem.
-int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_t st)
+// The depth of least modelled time for one problem; `model` receives the
+// modelled seconds of every depth tried (INFINITY elsewhere).
+int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_t st,
+                   double (*model)[AXF_MAX_DEPTH + 2] = nullptr)
 {
+    if (model)
+        for (double &v : *model) v = INFINITY;
     std::vector<double> rs(pb.ns), zs(pb.ns), rf(pb.nf), zf(pb.nf);
     AXF_HIP(hipMemcpyAsync(rs.data(), pb.r_src, pb.ns * sizeof(double), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipMemcpyAsync(zs.data(), pb.z_src, pb.ns * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -256,10 +260,187 @@ int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_
         const Work w = count_work(rs, zs, rf, zf, sq, d);
         const double t = w.near * pb.nrhs * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
                          (double)(pb.ns + pb.nf) * C * r.point;
+        if (model) (*model)[d] = t;
         if (t < best_t) {
             best_t = t;
             best = d;
         }
+    }
+    return best;
+}
+
+// Descriptors and merged work queues of a set of plans (problem i of the
+// queues is plans[i], evaluating S[i] into phi[i]), in one arena; the
+// uploads are queued on `st`.
+void build_queues(const std::vector<Plan *> &plans, const std::vector<const double *> &S,
+                  const std::vector<double *> &phi, int M, int nmodes, int tb, Arena &mem, BatchQueues &q,
+                  hipStream_t st)
+{
+    const int nprob = (int)plans.size();
+    std::vector<ProbDev> pd(nprob);
+    std::vector<int2> qg, qp, ql;
+    std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qs(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1);
+    int maxd = 2;
+    for (int i = 0; i < nprob; ++i) {
+        const Plan &pl = *plans[i];
+        maxd = std::max(maxd, pl.d);
+        fill_probdev(pl, S[i], phi[i], pd[i]);
+        int64_t ge = pl.src.n * pl.Cs;
+        for (int64_t k = 0; k * 256 < ge; ++k) qg.push_back(make_int2(i, (int)k));
+        for (int k = 0; k < pl.src.nocc[pl.d] * p2m_pairs(pl.C); ++k) qp.push_back(make_int2(i, k));
+        for (int t = 1; pl.d - t >= 2; ++t)
+            for (int k = 0; k < pl.src.nocc[pl.d - t] * pl.C; ++k) qm[t].push_back(make_int2(i, k));
+        for (int l = 2; l <= pl.d; ++l) {
+            for (int k = 0; k < pl.fld.nocc[l] * pl.C; ++k) qlt[l].push_back(make_int2(i, k));
+            for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k) qs[l].push_back(make_int2(i, k));
+        }
+        for (int k = 0; k < pl.fld.nchunks; ++k) ql.push_back(make_int2(i, k));
+    }
+    Sizer sz;
+    sz.add<ProbDev>(nprob);
+    sz.add<int2>(qg.size() + 1);
+    sz.add<int2>(qp.size() + 1);
+    sz.add<int2>(ql.size() + 1);
+    for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
+        sz.add<int2>(qm[l].size() + 1);
+        sz.add<int2>(qs[l].size() + 1);
+        sz.add<int2>(qlt[l].size() + 1);
+    }
+    mem = arena_acquire(sz.bytes + 4096);
+    q = BatchQueues();
+    ProbDev *dp = mem.take<ProbDev>(nprob);
+    auto up = [&](const std::vector<int2> &v, int2 *&dst, int &n) {
+        dst = mem.take<int2>(v.size() + 1);
+        n = (int)v.size();
+        if (n) AXF_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    };
+    AXF_HIP(hipMemcpyAsync(dp, pd.data(), sizeof(ProbDev) * nprob, hipMemcpyHostToDevice, st));
+    up(qg, q.gather, q.ngather);
+    up(qp, q.p2m, q.np2m);
+    up(ql, q.leaf, q.nleaf);
+    for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
+        up(qm[l], q.m2m[l], q.nm2m[l]);
+        up(qs[l], q.s2l[l], q.ns2l[l]);
+        up(qlt[l], q.l2l[l], q.nl2l[l]);
+    }
+    AXF_HIP(hipStreamSynchronize(st));   // the host images go out of scope
+    q.probs = dp;
+    q.M = M;
+    q.nmodes = nmodes;
+    q.nmb = mode_bucket(nmodes);
+    q.TS = (M + 1) * (M + 1) * (M + 1);
+    q.maxd = maxd;
+    q.chistar = plans[0]->chistar;
+    q.tb = tb;
+}
+
+// Problems with at least this many points get their depth from trial
+// evaluations (the modelled depth, then its neighbour the model ranks next,
+// then further in whichever direction improves); smaller ones take the
+// modelled depth.
+constexpr int64_t kTrialPoints = 2000;
+
+// One problem evaluated through the batch kernels at depth d (a one-problem
+// queue, an eager launch on `st`): the plan, and the time of one run.
+Plan *trial_plan(const axf_problem &pb, axf_params pp, int d, const BatchSide &side, hipStream_t st, double &sec)
+{
+    pp.depth = d;
+    Plan *pl = new Plan();
+    Arena mem;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        arena_release(mem);
+    };
+    try {
+        plan_build(*pl, pp, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
+        if (pl->tables_ready) AXF_HIP(hipEventSynchronize(pl->tables_ready));
+        BatchQueues q;
+        build_queues({pl}, {pb.S}, {pb.phi}, pp.order, pp.n_modes, pl->tb, mem, q, st);
+        AXF_HIP(hipEventCreate(&e0));
+        AXF_HIP(hipEventCreate(&e1));
+        AXF_HIP(hipEventRecord(e0, st));
+        run_batch(q, st, &side);
+        AXF_HIP(hipEventRecord(e1, st));
+        AXF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        AXF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        sec = 1e-3 * ms;
+    } catch (...) {
+        cleanup();
+        plan_release(pl);
+        delete pl;
+        throw;
+    }
+    cleanup();
+    return pl;
+}
+
+// The plan of one autotuned problem.
+Plan *tune_problem(const axf_problem &pb, const axf_params &pp, const Rates &rates, const BatchSide &side,
+                   hipStream_t st)
+{
+    double model[AXF_MAX_DEPTH + 2];
+    const int d0 = autotune_depth(pb, pp.n_modes, rates, st, &model);
+    const double npts = (double)std::max(pb.ns, pb.nf);
+    if (std::max(pb.ns, pb.nf) < kTrialPoints) {
+        axf_params p1 = pp;
+        p1.depth = d0;
+        Plan *pl = new Plan();
+        try {
+            plan_build(*pl, p1, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
+        } catch (...) {
+            plan_release(pl);
+            delete pl;
+            throw;
+        }
+        return pl;
+    }
+    Plan *best = nullptr;
+    int bestd = d0;
+    double bests = INFINITY;
+    std::vector<int> tried;
+    // true when depth d was tried and became the best
+    auto trial = [&](int d) -> bool {
+        if (d < 2 || d > AXF_MAX_DEPTH || (d > 2 && npts / std::pow(4.0, d - 1) < 1.0)) return false;
+        if (std::find(tried.begin(), tried.end(), d) != tried.end()) return false;
+        tried.push_back(d);
+        double sec = INFINITY;
+        Plan *p = trial_plan(pb, pp, d, side, st, sec);
+        if (!best || sec < bests) {
+            if (best) {
+                plan_release(best);
+                delete best;
+            }
+            best = p;
+            bestd = d;
+            bests = sec;
+            return true;
+        }
+        plan_release(p);
+        delete p;
+        return false;
+    };
+    try {
+        trial(d0);
+        const int lo = d0 - 1, hi = d0 + 1;
+        const double mlo = lo >= 2 ? model[lo] : INFINITY, mhi = model[hi];
+        const int first = mlo <= mhi ? lo : hi, second = first == lo ? hi : lo;
+        int dir = 0;
+        if (trial(first)) {
+            dir = first - d0;
+        } else if (trial(second)) {
+            dir = second - d0;
+        }
+        while (dir != 0 && trial(bestd + dir)) {
+        }
+    } catch (...) {
+        if (best) {
+            plan_release(best);
+            delete best;
+        }
+        throw;
     }
     return best;
 }
@@ -281,6 +462,7 @@ struct axf_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    BatchSide side;              // the near field's branch of the graph
 };
 
 static void batch_free(axf_batch *b)
@@ -290,6 +472,9 @@ static void batch_free(axf_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->side.stream) (void)hipStreamDestroy(b->side.stream);
+    if (b->side.fork) (void)hipEventDestroy(b->side.fork);
+    if (b->side.join) (void)hipEventDestroy(b->side.join);
     for (Plan *pl : b->plans) {
         plan_release(pl);
         delete pl;
@@ -352,88 +537,48 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             }
         }
         if (tune && tb_given) rates = measured_rates(params->order, params->n_modes, b->tb, st);
-        int maxd = 2;
+        AXF_HIP(hipStreamCreateWithFlags(&b->side.stream, hipStreamNonBlocking));
+        AXF_HIP(hipEventCreateWithFlags(&b->side.fork, hipEventDisableTiming));
+        AXF_HIP(hipEventCreateWithFlags(&b->side.join, hipEventDisableTiming));
         for (int i = 0; i < nprob; ++i) {
             const axf_problem &pb = problems[i];
             axf_params pp = *params;
             pp.nrhs = pb.nrhs;
             pp.flags = AXF_TILE(b->tb);
-            if (pb.depth != 0) {
-                pp.depth = pb.depth;
-            } else if (params->flags & AXF_BATCH_NO_AUTOTUNE) {
-                pp.depth = 0;
+            Plan *pl = nullptr;
+            if (pb.depth != 0 || !tune) {
+                pp.depth = pb.depth;          // 0 without the autotuner: the max_leaf rule
+                pl = new Plan();
+                try {
+                    plan_build(*pl, pp, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
+                } catch (...) {
+                    plan_release(pl);
+                    delete pl;
+                    throw;
+                }
             } else {
-                pp.depth = autotune_depth(pb, params->n_modes, rates, st);
+                pl = tune_problem(pb, pp, rates, b->side, st);
             }
-            Plan *pl = new Plan();
             b->plans.push_back(pl);
-            plan_build(*pl, pp, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
             b->depth.push_back(pl->d);
-            maxd = std::max(maxd, pl->d);
         }
         // the batch's passes do not wait on the table stream: tables first
         for (Plan *pl : b->plans)
             if (pl->tables_ready) AXF_HIP(hipEventSynchronize(pl->tables_ready));
-        // descriptors and merged queues
-        std::vector<ProbDev> pd(nprob);
-        std::vector<int2> qg, qp, ql;
-        std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qs(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1);
+        std::vector<const double *> Sv(nprob);
+        std::vector<double *> phiv(nprob);
         for (int i = 0; i < nprob; ++i) {
-            const Plan &pl = *b->plans[i];
-            fill_probdev(pl, problems[i].S, problems[i].phi, pd[i]);
-            int64_t ge = pl.src.n * pl.Cs;
-            for (int64_t k = 0; k * 256 < ge; ++k) qg.push_back(make_int2(i, (int)k));
-            for (int k = 0; k < pl.src.nocc[pl.d] * p2m_pairs(pl.C); ++k) qp.push_back(make_int2(i, k));
-            for (int t = 1; pl.d - t >= 2; ++t)
-                for (int k = 0; k < pl.src.nocc[pl.d - t] * pl.C; ++k) qm[t].push_back(make_int2(i, k));
-            for (int l = 2; l <= pl.d; ++l) {
-                for (int k = 0; k < pl.fld.nocc[l] * pl.C; ++k) qlt[l].push_back(make_int2(i, k));
-                for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k) qs[l].push_back(make_int2(i, k));
-            }
-            for (int k = 0; k < pl.fld.nchunks; ++k) ql.push_back(make_int2(i, k));
+            Sv[i] = problems[i].S;
+            phiv[i] = problems[i].phi;
         }
-        Sizer sz;
-        sz.add<ProbDev>(nprob);
-        sz.add<int2>(qg.size() + 1);
-        sz.add<int2>(qp.size() + 1);
-        sz.add<int2>(ql.size() + 1);
-        for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
-            sz.add<int2>(qm[l].size() + 1);
-            sz.add<int2>(qs[l].size() + 1);
-            sz.add<int2>(qlt[l].size() + 1);
-        }
-        b->qmem = arena_acquire(sz.bytes + 4096);
         BatchQueues &q = b->q;
-        ProbDev *dp = b->qmem.take<ProbDev>(nprob);
-        auto up = [&](const std::vector<int2> &v, int2 *&dst, int &n) {
-            dst = b->qmem.take<int2>(v.size() + 1);
-            n = (int)v.size();
-            if (n) AXF_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-        };
-        AXF_HIP(hipMemcpyAsync(dp, pd.data(), sizeof(ProbDev) * nprob, hipMemcpyHostToDevice, st));
-        up(qg, q.gather, q.ngather);
-        up(qp, q.p2m, q.np2m);
-        up(ql, q.leaf, q.nleaf);
-        for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
-            up(qm[l], q.m2m[l], q.nm2m[l]);
-            up(qs[l], q.s2l[l], q.ns2l[l]);
-            up(qlt[l], q.l2l[l], q.nl2l[l]);
-        }
-        AXF_HIP(hipStreamSynchronize(st));
-        q.probs = dp;
-        q.M = params->order;
-        q.nmodes = params->n_modes;
-        q.nmb = mode_bucket(params->n_modes);
-        q.TS = (params->order + 1) * (params->order + 1) * (params->order + 1);
-        q.maxd = maxd;
-        q.chistar = b->plans[0]->chistar;
-        q.tb = b->tb;
+        build_queues(b->plans, Sv, phiv, params->order, params->n_modes, b->tb, b->qmem, q, st);
         // one eager pass (sets kernel attributes), then capture the sequence
-        run_batch(q, st);
+        run_batch(q, st, &b->side);
         AXF_HIP(hipStreamSynchronize(st));
         AXF_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         AXF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        run_batch(q, b->cap);
+        run_batch(q, b->cap, &b->side);
         AXF_HIP(hipStreamEndCapture(b->cap, &b->graph));
         AXF_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         *out_batch = b;

@@ -1019,16 +1019,11 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
 // are staged in LDS and each wave evaluates one channel at its targets by
 // Horner's rule in z nested in Horner's rule in r (offsets in box units).
 constexpr int kL2PChannels = 4;
-__global__ __launch_bounds__(64 * kL2PChannels) void k_l2p(int M, int nmodes, int nrhs, int depth, double rlo,
-                                                           double zlo, double invh, const int4 *__restrict__ chunks,
-                                                           SideView tv, const double2 *__restrict__ loc,
-                                                           double2 *__restrict__ phi, int64_t ntot)
+__device__ __forceinline__ void l2p_body(int M, int nmodes, int nrhs, int depth, double rlo, double zlo, double invh,
+                                         const int4 ch, SideView tv, const double2 *__restrict__ loc,
+                                         double2 *__restrict__ phi, int64_t ntot, int grp, double2 *__restrict__ cf)
 {
-    extern __shared__ double2 cf[];          // [kL2PChannels][P]
     const int P = (M + 1) * (M + 2) / 2, C = nmodes * nrhs;
-    const int ngrp = (C + kL2PChannels - 1) / kL2PChannels;
-    const int ci = blockIdx.x / ngrp, grp = blockIdx.x - ci * ngrp;
-    const int4 ch = chunks[ci];
     const int c0 = grp * kL2PChannels, nc = min(kL2PChannels, C - c0);
     const double2 *lc = loc + ((int64_t)ch.x * C + c0) * P;
     for (int e = threadIdx.x; e < nc * P; e += blockDim.x) cf[e] = lc[e];
@@ -1056,6 +1051,18 @@ __global__ __launch_bounds__(64 * kL2PChannels) void k_l2p(int M, int nmodes, in
     const int64_t o = ((int64_t)q * nmodes + n) * ntot + tv.perm[t];
     const double2 v = phi[o];
     phi[o] = make_double2(v.x + ar, v.y + ai);
+}
+
+__global__ __launch_bounds__(64 * kL2PChannels) void k_l2p(int M, int nmodes, int nrhs, int depth, double rlo,
+                                                           double zlo, double invh, const int4 *__restrict__ chunks,
+                                                           SideView tv, const double2 *__restrict__ loc,
+                                                           double2 *__restrict__ phi, int64_t ntot)
+{
+    extern __shared__ double2 cf[];          // [kL2PChannels][P]
+    const int C = nmodes * nrhs;
+    const int ngrp = (C + kL2PChannels - 1) / kL2PChannels;
+    const int ci = blockIdx.x / ngrp, grp = blockIdx.x - ci * ngrp;
+    l2p_body(M, nmodes, nrhs, depth, rlo, zlo, invh, chunks[ci], tv, loc, phi, ntot, grp, cf);
 }
 
 // ---------------------------------------------------------------- direct
@@ -1299,7 +1306,9 @@ __global__ __launch_bounds__(256) void kb_l2l(const ProbDev *__restrict__ P, con
     }
 }
 
-template <int NMB>
+// PART 0: near field and local expansions; PART 1: near field only (the
+// local expansions follow in kb_l2p).
+template <int NMB, int PART>
 __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDev *__restrict__ P,
                                                                     const int2 *__restrict__ q, int n, int M,
                                                                     int nmodes, double chistar)
@@ -1308,9 +1317,26 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
         const int2 it = q[i];
         ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
         __syncthreads();
-        leaf_body<NMB, 0>(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, chistar,
-                          pd.chunks, view_of(pd.tv), view_of(pd.sv), pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr, nullptr, nullptr,
-                          nullptr, nullptr, nullptr, pd.nf, pd.Cs, it.y);
+        leaf_body<NMB, 0, PART>(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, chistar,
+                                pd.chunks, view_of(pd.tv), view_of(pd.sv), pd.srinv, pd.Sg, pd.loc[pd.d], pd.phi, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, pd.nf, pd.Cs, it.y);
+    }
+}
+
+// Local expansions of every chunk of the leaf queue, all channel groups.
+__global__ __launch_bounds__(64 * kL2PChannels) void kb_l2p(const ProbDev *__restrict__ P,
+                                                            const int2 *__restrict__ q, int n, int M, int nmodes)
+{
+    extern __shared__ double2 cf[];
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
+        const int C = nmodes * pd.nrhs, ngrp = (C + kL2PChannels - 1) / kL2PChannels;
+        for (int g = 0; g < ngrp; ++g) {
+            __syncthreads();
+            l2p_body(M, nmodes, pd.nrhs, pd.d, pd.rlo, pd.zlo, (double)(1 << pd.d) * pd.invL, pd.chunks[it.y],
+                     view_of(pd.tv), pd.loc[pd.d], pd.phi, pd.nf, g, cf);
+        }
     }
 }
 
@@ -1327,19 +1353,17 @@ void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
     kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
 }
 
-template <int NMB>
+template <int NMB, int PART>
 void launch_leaf_batch(const BatchQueues &bq, hipStream_t st)
 {
     constexpr size_t shm = leaf_lds_bytes<NMB, 0>();
     static bool attr[64] = {};
     int dev = 0;
     AXF_HIP(hipGetDevice(&dev));
-    if (shm > 65536 && !attr[dev & 63]) {
-        AXF_HIP(hipFuncSetAttribute((const void *)kb_leaf<NMB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        attr[dev & 63] = true;
-    }
+    allow_lds(kb_leaf<NMB, PART>, shm, dev, attr);
     int g = std::min(bq.nleaf, kPersistBlocks);
-    kb_leaf<NMB><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes, bq.chistar);
+    kb_leaf<NMB, PART><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes,
+                                                                   bq.chistar);
 }
 
 // ------------------------------------------------------------- census
@@ -1490,7 +1514,7 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
     // latency-bound and leave issue slots to the other); it is started after
     // the short upward pass so that it does not hold the CUs that pass
     // needs; the local expansions are added once both are done
-    const bool split = out.mode == 0 && !out.fused && tgt.nchunks > 0;
+    const bool split = out.mode == 0 && !out.fused && pl.overlap && tgt.nchunks > 0;
     SideView sv = view_of(src);
     if (src.nocc[d] > 0) {
         PhaseTimer tm(pl, st, AXF_PHASE_P2M);
@@ -1569,7 +1593,7 @@ void run_direct(Plan &pl, const Side &src, const Side &tgt, const double *S, con
 #undef AXF_DIR
 }
 
-void run_batch(const BatchQueues &bq, hipStream_t st)
+void run_batch(const BatchQueues &bq, hipStream_t st, const BatchSide *side)
 {
     if (bq.ngather)
         kb_gather<<<std::min(bq.ngather, kPersistBlocks), 256, 0, st>>>(bq.probs, bq.gather, bq.ngather, bq.nmodes);
@@ -1577,6 +1601,18 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
     for (int t = 1; t <= bq.maxd - 2; ++t)
         if (bq.nm2m[t])
             kb_m2m<<<std::min(bq.nm2m[t], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.m2m[t], bq.nm2m[t], bq.M, t);
+    // the near field of every problem beside the downward pass (as in
+    // run_fmm), when a second stream is given
+    const bool split = side != nullptr && bq.nleaf > 0;
+    if (split) {
+        AXF_HIP(hipEventRecord(side->fork, st));
+        AXF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+#define AXF_NEARB(B)                                    \
+    if (bq.nmb == B) launch_leaf_batch<B, 1>(bq, side->stream);
+        AXF_BUCKETS(AXF_NEARB)
+#undef AXF_NEARB
+        AXF_HIP(hipEventRecord(side->join, side->stream));
+    }
     for (int l = 2; l <= bq.maxd; ++l) {
         if (bq.nl2l[l])
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
@@ -1591,10 +1627,15 @@ void run_batch(const BatchQueues &bq, hipStream_t st)
 #undef AXF_S2L_LAUNCH4
 #undef AXF_S2L_LAUNCH8
     }
-    if (bq.nleaf) {
+    if (split) {
+        AXF_HIP(hipStreamWaitEvent(st, side->join, 0));
+        const int P = (bq.M + 1) * (bq.M + 2) / 2;
+        kb_l2p<<<std::min(bq.nleaf, kPersistBlocks), 64 * kL2PChannels, sizeof(double2) * kL2PChannels * P, st>>>(
+            bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes);
+    } else if (bq.nleaf) {
 #define AXF_LEAFB(B)                          \
     if (bq.nmb == B) {                        \
-        launch_leaf_batch<B>(bq, st);         \
+        launch_leaf_batch<B, 0>(bq, st);      \
     }
         AXF_BUCKETS(AXF_LEAFB)
 #undef AXF_LEAFB

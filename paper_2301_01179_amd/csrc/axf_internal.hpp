@@ -163,6 +163,7 @@ struct Plan {
     int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
     int nmb = 4, Cs = 4;        // mode bucket and padded channels per point in Sg
     int tb = kDefaultTile;      // S2L tile width (target boxes per tile)
+    bool overlap = true;        // near field beside the downward pass (second stream)
     double rlo = 0, zlo = 0, L = 1, invL = 1;
     double rmax = 0;                     // largest ring radius of both sets
     int tab_smax[AXF_MAX_DEPTH + 1] = {};   // last radial station with tables, per level
@@ -324,7 +325,13 @@ void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd);
 // Pair census of the near field (or, sampled, of the direct sum) with the
 // field points as targets: [pairs, backward pairs, AGM iterations, steps].
 void pair_census(Plan &pl, bool direct, double out[4], hipStream_t st);
-void run_batch(const BatchQueues &bq, hipStream_t st);
+// A second stream and two events with which run_batch runs the near field
+// beside the downward pass.
+struct BatchSide {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+void run_batch(const BatchQueues &bq, hipStream_t st, const BatchSide *side);
 
 }  // namespace axf
 

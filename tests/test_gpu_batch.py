@@ -137,3 +137,57 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(axf.AxfError):
         axf.Batch([(r, z, r, z, S)], 3, 30)          # order beyond the maximum
 
+
+
+def _median_ms(fn, reps=7):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+@gpu
+def test_batch_autotuner_near_best():
+    """On three problems of the batched workload's shape (ring box, modes
+    0..16, M = 12), the autotuner's (depth, tile width) for each runs within
+    10% of the best of (depth d* - 1, d*, d* + 1) x (tile 2, 4, 8), each timed
+    as a one-problem batch (graph replay), and gives the oracle's values."""
+    need_gpu()
+    axf = _axf()
+    nmodes, M = 17, 12
+    probs = []
+    for i, (n, q) in enumerate([(6000, 1), (40000, 2), (150000, 4)]):
+        r, z, S = inputs.ring_box(n, nmodes, nrhs=q, seed=300 + i)
+        probs.append((r, z, r, z, S))
+    b = axf.Batch(probs, nmodes, M)
+    depths, tile = b.depths(), b.tile()
+    print("chosen depths", depths, "tile", tile, flush=True)
+    b.close()
+    for i, pb in enumerate(probs):
+        times = {}
+        for d in (depths[i] - 1, depths[i], depths[i] + 1):
+            if d < 2:
+                continue
+            for tb in (2, 4, 8):
+                one = axf.Batch([pb + (d,)], nmodes, M, tile=tb)
+                one.launch()
+                times[(d, tb)] = _median_ms(one.launch)
+                one.close()
+        best = min(times.values())
+        chosen = times[(depths[i], tile)]
+        print("problem", i, "times", {k: round(v, 3) for k, v in times.items()}, flush=True)
+        assert chosen <= 1.10 * best, (i, chosen, best)
+    # the tuned batch still computes the FMM
+    r, z, _, _, S = probs[0]
+    b = axf.Batch(probs[:1], nmodes, M)
+    phi = to_np(b.launch()[0])
+    idx = np.arange(0, r.size, 997)
+    ref = O.fmm_points(r, z, r, z, S, M, b.depths()[0], idx)
+    assert rel_err(phi[..., idx], ref).max() < TOL
+    b.close()
