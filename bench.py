@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 200k-ring adjoint measurement")
     ap.add_argument("--no-curve", action="store_true", help="skip the 1M-ring generator-curve measurement")
+    ap.add_argument("--no-leaf-rule", action="store_true", help="skip the <= max_leaf depth's measurement")
+    ap.add_argument("--no-standalone", action="store_true",
+                    help="skip the kernels' standalone timing (near field after the downward pass)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -440,18 +443,20 @@ def main():
     # the kernels on their own: the same plan with the near field after the
     # downward pass on one stream (AXF_NO_OVERLAP), so that each kernel's
     # launch time is not shared with the other's
-    ser = axf.Plan(rs, zs, rf, zf, nm, args.order, depth=depth, tile=tile, overlap=False)
-    ser.evaluate(S)
-    torch.cuda.synchronize()
-    ser.set_timing(True)
-    for _ in range(args.steps):
+    t_ser = {}
+    if not args.no_standalone:
+        ser = axf.Plan(rs, zs, rf, zf, nm, args.order, depth=depth, tile=tile, overlap=False)
         ser.evaluate(S)
-    torch.cuda.synchronize()
-    t_ser = ser.read_timing()
-    ser.set_timing(False)
-    ser.close()
+        torch.cuda.synchronize()
+        ser.set_timing(True)
+        for _ in range(args.steps):
+            ser.evaluate(S)
+        torch.cuda.synchronize()
+        t_ser = ser.read_timing()
+        ser.set_timing(False)
+        ser.close()
     standalone = {}
-    for ph in ("s2l", "leaf"):
+    for ph in [p for p in ("s2l", "leaf") if p in t_ser]:
         ms_ph, n_ph = t_ser[ph]
         if ms_ph > 0:
             a = flops[ph] / (ms_ph / 1e3 / args.steps) / 1e12
@@ -481,7 +486,7 @@ def main():
     rule_plan = axf.Plan(rs, zs, rf, zf, nm, 0, depth=0, max_leaf=args.max_leaf)
     d_rule = rule_plan.info()["depth"]
     rule_plan.close()
-    if d_rule != depth:
+    if d_rule != depth and not args.no_leaf_rule:
         pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, max(3, args.steps // 2), 1,
                                         tile)
         phir_s = phir[..., sample].cpu().numpy()
