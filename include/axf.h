@@ -279,6 +279,7 @@ typedef struct {
     double *phi;                   /* device complex128 [nrhs][n_modes][nf] */
     int32_t nrhs;                  /* 1..AXF_MAX_RHS */
     int32_t depth;                 /* 0 = chosen by the autotuner */
+    int32_t tile;                  /* S2L tile width 2, 4 or 8; 0 = the batch's choice */
 } axf_problem;
 
 typedef struct axf_batch axf_batch;
@@ -288,17 +289,21 @@ typedef struct axf_batch axf_batch;
  * problem); params->max_leaf is used where a problem's depth is 0 and the
  * autotuner is disabled (flags bit AXF_BATCH_NO_AUTOTUNE).  The autotuner
  * measures, on the device, the seconds per near-field pair, per S2L unit,
- * per shifted box and per point of a probe problem (once per process for a
- * given order, mode count and tile width), takes the S2L tile width whose
- * probe ran fastest unless params->flags holds AXF_TILE(tb) (one width for
- * the whole batch), and gives every problem of depth 0 the depth of least
- * modelled time over its exactly counted work; problems of 2,000 points or
- * more then time trial evaluations through the batch kernels at that depth
- * and its neighbours (continuing in the direction that improves) and keep
- * the fastest.  Those trials read S and overwrite phi.  The problem array is
- * host memory and is copied; the S and phi buffers it names must stay valid
- * for every launch.  The graph runs the near field of all problems on a
- * branch beside the downward pass.  Synchronises `stream`. */
+ * per shifted box and per point of a probe problem at each S2L tile width
+ * (once per process for a given order, mode count and width) and gives
+ * every problem of depth 0 the (depth, width) of least modelled time over
+ * its exactly counted work; problems of 2,000 points or more then time
+ * trial evaluations through the batch kernels (that pair, neighbouring
+ * depths at that width, continuing in the direction that improves, then the
+ * other widths at the fastest depth) and keep the fastest.  Those trials
+ * read S and overwrite phi.  A problem's own `tile` fixes its width (the
+ * autotuner then searches depths only); AXF_TILE(tb) in params->flags fixes
+ * the width of every problem that names none; otherwise problems with a
+ * given depth take the width whose probe S2L ran fastest (4 without the
+ * autotuner).  The
+ * problem array is host memory and is copied; the S and phi buffers it names
+ * must stay valid for every launch.  The graph runs the near field of all
+ * problems on a branch beside the downward pass.  Synchronises `stream`. */
 #define AXF_BATCH_NO_AUTOTUNE 1u
 axf_status axf_batch_create(const axf_params *params, int32_t nprob,
                             const axf_problem *problems, void *stream,
@@ -314,8 +319,8 @@ axf_status axf_batch_launch_plain(axf_batch *batch, void *stream);
 /* Depth the batch chose for problem `i` (host output). */
 axf_status axf_batch_problem_depth(const axf_batch *batch, int32_t i, int32_t *depth);
 
-/* S2L tile width the batch runs with (host output). */
-axf_status axf_batch_tile(const axf_batch *batch, int32_t *tile);
+/* S2L tile width of problem `i` (host output). */
+axf_status axf_batch_problem_tile(const axf_batch *batch, int32_t i, int32_t *tile);
 
 void axf_batch_destroy(axf_batch *batch);
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "axf_evaluate", "axf_evaluate_noalloc", "axf_evaluate_grad",
     "axf_evaluate_direct", "axf_adjoint", "axf_plan_info", "axf_plan_level_info",
     "axf_batch_create", "axf_batch_launch", "axf_batch_launch_plain",
-    "axf_batch_problem_depth", "axf_batch_tile", "axf_batch_destroy", "axf_status_string", "axf_last_error",
+    "axf_batch_problem_depth", "axf_batch_problem_tile", "axf_batch_destroy", "axf_status_string", "axf_last_error",
     "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
     "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis",
 ]
@@ -52,7 +52,7 @@ class Problem(ctypes.Structure):
                 ("r_src", ctypes.c_void_p), ("z_src", ctypes.c_void_p),
                 ("r_fld", ctypes.c_void_p), ("z_fld", ctypes.c_void_p),
                 ("S", ctypes.c_void_p), ("phi", ctypes.c_void_p),
-                ("nrhs", ctypes.c_int32), ("depth", ctypes.c_int32)]
+                ("nrhs", ctypes.c_int32), ("depth", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 _lib = None
@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.axf_batch_launch.argtypes = [vp, vp]
     lib.axf_batch_launch_plain.argtypes = [vp, vp]
     lib.axf_batch_problem_depth.argtypes = [vp, i32, P(i32)]
-    lib.axf_batch_tile.argtypes = [vp, P(i32)]
+    lib.axf_batch_problem_tile.argtypes = [vp, i32, P(i32)]
     lib.axf_batch_destroy.argtypes = [vp]
     lib.axf_batch_destroy.restype = None
     lib.axf_status_string.argtypes = [ctypes.c_int]
@@ -103,7 +103,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("axf_plan_create", "axf_plan_set_workspace", "axf_set_cache_limit", "axf_evaluate",
                  "axf_evaluate_noalloc", "axf_evaluate_grad", "axf_evaluate_direct",
                  "axf_adjoint", "axf_plan_info", "axf_plan_level_info", "axf_batch_create",
-                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth", "axf_batch_tile",
+                 "axf_batch_launch", "axf_batch_launch_plain", "axf_batch_problem_depth", "axf_batch_problem_tile",
                  "axf_plan_set_timing", "axf_plan_read_timing", "axf_plan_work", "axf_plan_table",
                  "axf_plan_census", "axf_azimuthal_analysis", "axf_azimuthal_synthesis"):
         getattr(lib, name).restype = ctypes.c_int
@@ -348,10 +348,11 @@ class Plan:
 class Batch:
     """Many independent problems evaluated by one captured launch sequence.
 
-    problems: sequence of (r_src, z_src, r_fld, z_fld, S) or
-    (r_src, z_src, r_fld, z_fld, S, depth); S complex [nrhs, n_modes, ns].
+    problems: sequence of (r_src, z_src, r_fld, z_fld, S), optionally
+    followed by depth and then S2L tile width; S complex [nrhs, n_modes, ns].
     Depth 0 lets the library's autotuner choose (or the max_leaf rule when
-    autotune is False).  The strength tensors are kept and read at every
+    autotune is False); tile width 0 leaves it to the batch (the `tile`
+    argument, else the autotuner).  The strength tensors are kept and read at every
     launch, so they may be updated in place between launches; `outputs`
     holds the potentials [nrhs, n_modes, nf] of each problem.
     """
@@ -368,6 +369,7 @@ class Batch:
         for i, pb in enumerate(problems):
             rs, zs, rf, zf, S = pb[:5]
             depth = pb[5] if len(pb) > 5 else 0
+            ptile = pb[6] if len(pb) > 6 else 0
             rs, zs, rf, zf = (_coords(a, dev) for a in (rs, zs, rf, zf))
             S = torch.as_tensor(S, device=dev).to(torch.complex128)
             if S.dim() == 2:
@@ -378,7 +380,7 @@ class Batch:
                 raise ValueError(f"problem {i}: S must be [nrhs, {n_modes}, {rs.numel()}]")
             phi = torch.empty((nrhs, n_modes, rf.numel()), dtype=torch.complex128, device=dev)
             arr[i] = Problem(rs.numel(), rf.numel(), rs.data_ptr(), zs.data_ptr(), rf.data_ptr(),
-                             zf.data_ptr(), S.data_ptr(), phi.data_ptr(), nrhs, depth)
+                             zf.data_ptr(), S.data_ptr(), phi.data_ptr(), nrhs, depth, ptile)
             self._keep.append((rs, zs, rf, zf))
             self.strengths.append(S)
             self.outputs.append(phi)
@@ -407,11 +409,14 @@ class Batch:
             out.append(d.value)
         return out
 
-    def tile(self) -> int:
-        """S2L tile width the batch runs with."""
-        t = ctypes.c_int32()
-        _check(_lib.axf_batch_tile(self._h, ctypes.byref(t)), "axf_batch_tile")
-        return t.value
+    def tiles(self):
+        """S2L tile width of every problem."""
+        out = []
+        for i in range(len(self.outputs)):
+            t = ctypes.c_int32()
+            _check(_lib.axf_batch_problem_tile(self._h, i, ctypes.byref(t)), "axf_batch_problem_tile")
+            out.append(t.value)
+        return out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -20,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "axf_device.hpp"
@@ -237,13 +238,17 @@ Rates measured_rates(int M, int nmodes, int tb, hipStream_t st)
     return r;
 }
 
-// The depth of least modelled time for one problem; `model` receives the
-// modelled seconds of every depth tried (INFINITY elsewhere).
-int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_t st,
-                   double (*model)[AXF_MAX_DEPTH + 2] = nullptr)
+// Modelled seconds of problem pb at every depth and tile width: the exact
+// work counts of each depth priced at the probe rates of each width
+// (rates[t] for width kTiles[t]; a width whose rates are absent, s2l_unit
+// zero, is skipped).  Entries that are not modelled hold INFINITY.  Returns
+// the (depth, tile index) of least modelled time.
+using Model = double[AXF_MAX_DEPTH + 2][3];
+std::pair<int, int> autotune_model(const axf_problem &pb, int nmodes, const Rates *rates, hipStream_t st,
+                                   Model &model)
 {
-    if (model)
-        for (double &v : *model) v = INFINITY;
+    for (auto &row : model)
+        for (double &v : row) v = INFINITY;
     std::vector<double> rs(pb.ns), zs(pb.ns), rf(pb.nf), zf(pb.nf);
     AXF_HIP(hipMemcpyAsync(rs.data(), pb.r_src, pb.ns * sizeof(double), hipMemcpyDeviceToHost, st));
     AXF_HIP(hipMemcpyAsync(zs.data(), pb.z_src, pb.ns * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -252,18 +257,22 @@ int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_
     AXF_HIP(hipStreamSynchronize(st));
     const Square sq = plan_square(rs, zs, rf, zf);
     const double C = (double)nmodes * pb.nrhs;
-    int best = 2;
+    std::pair<int, int> best{2, tile_index(kDefaultTile)};
     double best_t = INFINITY;
     const double npts = (double)std::max(pb.ns, pb.nf);
     for (int d = 2; d <= AXF_MAX_DEPTH; ++d) {
         if (d > 2 && npts / std::pow(4.0, d - 1) < 1.0) break;   // deeper than one point per box
         const Work w = count_work(rs, zs, rf, zf, sq, d);
-        const double t = w.near * pb.nrhs * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
-                         (double)(pb.ns + pb.nf) * C * r.point;
-        if (model) (*model)[d] = t;
-        if (t < best_t) {
-            best_t = t;
-            best = d;
+        for (int t = 0; t < 3; ++t) {
+            const Rates &r = rates[t];
+            if (r.s2l_unit <= 0) continue;
+            const double tm = w.near * pb.nrhs * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
+                              (double)(pb.ns + pb.nf) * C * r.point;
+            model[d][t] = tm;
+            if (tm < best_t) {
+                best_t = tm;
+                best = {d, t};
+            }
         }
     }
     return best;
@@ -273,13 +282,12 @@ int autotune_depth(const axf_problem &pb, int nmodes, const Rates &r, hipStream_
 // queues is plans[i], evaluating S[i] into phi[i]), in one arena; the
 // uploads are queued on `st`.
 void build_queues(const std::vector<Plan *> &plans, const std::vector<const double *> &S,
-                  const std::vector<double *> &phi, int M, int nmodes, int tb, Arena &mem, BatchQueues &q,
-                  hipStream_t st)
+                  const std::vector<double *> &phi, int M, int nmodes, Arena &mem, BatchQueues &q, hipStream_t st)
 {
     const int nprob = (int)plans.size();
     std::vector<ProbDev> pd(nprob);
     std::vector<int2> qg, qp, ql;
-    std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qs(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1);
+    std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1), qs(3 * (AXF_MAX_DEPTH + 1));
     int maxd = 2;
     for (int i = 0; i < nprob; ++i) {
         const Plan &pl = *plans[i];
@@ -292,7 +300,8 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
             for (int k = 0; k < pl.src.nocc[pl.d - t] * pl.C; ++k) qm[t].push_back(make_int2(i, k));
         for (int l = 2; l <= pl.d; ++l) {
             for (int k = 0; k < pl.fld.nocc[l] * pl.C; ++k) qlt[l].push_back(make_int2(i, k));
-            for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k) qs[l].push_back(make_int2(i, k));
+            for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k)
+                qs[3 * l + tile_index(pl.tb)].push_back(make_int2(i, k));
         }
         for (int k = 0; k < pl.fld.nchunks; ++k) ql.push_back(make_int2(i, k));
     }
@@ -303,8 +312,8 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
     sz.add<int2>(ql.size() + 1);
     for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
         sz.add<int2>(qm[l].size() + 1);
-        sz.add<int2>(qs[l].size() + 1);
         sz.add<int2>(qlt[l].size() + 1);
+        for (int t = 0; t < 3; ++t) sz.add<int2>(qs[3 * l + t].size() + 1);
     }
     mem = arena_acquire(sz.bytes + 4096);
     q = BatchQueues();
@@ -320,8 +329,8 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
     up(ql, q.leaf, q.nleaf);
     for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
         up(qm[l], q.m2m[l], q.nm2m[l]);
-        up(qs[l], q.s2l[l], q.ns2l[l]);
         up(qlt[l], q.l2l[l], q.nl2l[l]);
+        for (int t = 0; t < 3; ++t) up(qs[3 * l + t], q.s2l[l][t], q.ns2l[l][t]);
     }
     AXF_HIP(hipStreamSynchronize(st));   // the host images go out of scope
     q.probs = dp;
@@ -331,20 +340,23 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
     q.TS = (M + 1) * (M + 1) * (M + 1);
     q.maxd = maxd;
     q.chistar = plans[0]->chistar;
-    q.tb = tb;
 }
 
-// Problems with at least this many points get their depth from trial
-// evaluations (the modelled depth, then its neighbour the model ranks next,
-// then further in whichever direction improves); smaller ones take the
-// modelled depth.
+// Problems with at least this many points get their depth and tile width
+// from trial evaluations: the modelled (depth, width), then at that width the
+// neighbouring depth the model ranks next, further in whichever direction
+// improves, and last the other widths at the fastest depth.  Smaller
+// problems take the modelled pair.
 constexpr int64_t kTrialPoints = 2000;
 
-// One problem evaluated through the batch kernels at depth d (a one-problem
-// queue, an eager launch on `st`): the plan, and the time of one run.
-Plan *trial_plan(const axf_problem &pb, axf_params pp, int d, const BatchSide &side, hipStream_t st, double &sec)
+// One problem evaluated through the batch kernels at depth d and S2L tile
+// width tb (a one-problem queue, an eager launch on `st`): the plan, and the
+// time of one run.
+Plan *trial_plan(const axf_problem &pb, axf_params pp, int d, int tb, const BatchSide &side, hipStream_t st,
+                 double &sec)
 {
     pp.depth = d;
+    pp.flags = AXF_TILE(tb);
     Plan *pl = new Plan();
     Arena mem;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -357,7 +369,7 @@ Plan *trial_plan(const axf_problem &pb, axf_params pp, int d, const BatchSide &s
         plan_build(*pl, pp, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
         if (pl->tables_ready) AXF_HIP(hipEventSynchronize(pl->tables_ready));
         BatchQueues q;
-        build_queues({pl}, {pb.S}, {pb.phi}, pp.order, pp.n_modes, pl->tb, mem, q, st);
+        build_queues({pl}, {pb.S}, {pb.phi}, pp.order, pp.n_modes, mem, q, st);
         AXF_HIP(hipEventCreate(&e0));
         AXF_HIP(hipEventCreate(&e1));
         AXF_HIP(hipEventRecord(e0, st));
@@ -377,16 +389,19 @@ Plan *trial_plan(const axf_problem &pb, axf_params pp, int d, const BatchSide &s
     return pl;
 }
 
-// The plan of one autotuned problem.
-Plan *tune_problem(const axf_problem &pb, const axf_params &pp, const Rates &rates, const BatchSide &side,
+// The plan of one autotuned problem; rates[t] are the probe rates of tile
+// width kTiles[t] (s2l_unit zero: that width is not considered).
+Plan *tune_problem(const axf_problem &pb, const axf_params &pp, const Rates *rates, const BatchSide &side,
                    hipStream_t st)
 {
-    double model[AXF_MAX_DEPTH + 2];
-    const int d0 = autotune_depth(pb, pp.n_modes, rates, st, &model);
+    Model model;
+    const std::pair<int, int> m0 = autotune_model(pb, pp.n_modes, rates, st, model);
+    const int d0 = m0.first, t0 = m0.second;
     const double npts = (double)std::max(pb.ns, pb.nf);
     if (std::max(pb.ns, pb.nf) < kTrialPoints) {
         axf_params p1 = pp;
         p1.depth = d0;
+        p1.flags = AXF_TILE(kTiles[t0]);
         Plan *pl = new Plan();
         try {
             plan_build(*pl, p1, pb.ns, pb.r_src, pb.z_src, pb.nf, pb.r_fld, pb.z_fld, st);
@@ -400,14 +415,15 @@ Plan *tune_problem(const axf_problem &pb, const axf_params &pp, const Rates &rat
     Plan *best = nullptr;
     int bestd = d0;
     double bests = INFINITY;
-    std::vector<int> tried;
-    // true when depth d was tried and became the best
-    auto trial = [&](int d) -> bool {
+    std::vector<std::pair<int, int>> tried;
+    // true when (depth d, tile index t) was tried and became the best
+    auto trial = [&](int d, int t) -> bool {
         if (d < 2 || d > AXF_MAX_DEPTH || (d > 2 && npts / std::pow(4.0, d - 1) < 1.0)) return false;
-        if (std::find(tried.begin(), tried.end(), d) != tried.end()) return false;
-        tried.push_back(d);
+        if (rates[t].s2l_unit <= 0) return false;
+        if (std::find(tried.begin(), tried.end(), std::make_pair(d, t)) != tried.end()) return false;
+        tried.emplace_back(d, t);
         double sec = INFINITY;
-        Plan *p = trial_plan(pb, pp, d, side, st, sec);
+        Plan *p = trial_plan(pb, pp, d, kTiles[t], side, st, sec);
         if (!best || sec < bests) {
             if (best) {
                 plan_release(best);
@@ -423,18 +439,21 @@ Plan *tune_problem(const axf_problem &pb, const axf_params &pp, const Rates &rat
         return false;
     };
     try {
-        trial(d0);
+        trial(d0, t0);
         const int lo = d0 - 1, hi = d0 + 1;
-        const double mlo = lo >= 2 ? model[lo] : INFINITY, mhi = model[hi];
+        const double mlo = lo >= 2 ? model[lo][t0] : INFINITY, mhi = model[hi][t0];
         const int first = mlo <= mhi ? lo : hi, second = first == lo ? hi : lo;
         int dir = 0;
-        if (trial(first)) {
+        if (trial(first, t0)) {
             dir = first - d0;
-        } else if (trial(second)) {
+        } else if (trial(second, t0)) {
             dir = second - d0;
         }
-        while (dir != 0 && trial(bestd + dir)) {
+        while (dir != 0 && trial(bestd + dir, t0)) {
         }
+        const int dbest = bestd;
+        for (int t = 0; t < 3; ++t)
+            if (t != t0) trial(dbest, t);
     } catch (...) {
         if (best) {
             plan_release(best);
@@ -455,8 +474,8 @@ struct axf_batch {
     axf_params p{};
     std::vector<axf_problem> probs;
     std::vector<Plan *> plans;
-    std::vector<int> depth;
-    int tb = kDefaultTile;
+    std::vector<int> depth, tile;   // per problem
+    int tb = kDefaultTile;           // width of the problems with a given depth
     Arena qmem;
     BatchQueues q;
     hipGraph_t graph = nullptr;
@@ -505,6 +524,8 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
                         "problem " + std::to_string(i) + ": nrhs must be in 1..8");
             AXF_REQUIRE(pb.depth == 0 || (pb.depth >= 2 && pb.depth <= AXF_MAX_DEPTH), AXF_ERR_UNSUPPORTED,
                         "problem " + std::to_string(i) + ": depth must be 0 or in 2..11");
+            AXF_REQUIRE(pb.tile == 0 || s2l_tile_ok(pb.tile), AXF_ERR_UNSUPPORTED,
+                        "problem " + std::to_string(i) + ": S2L tile width must be 0, 2, 4 or 8");
             AXF_REQUIRE(pb.depth != 0 || !(params->flags & AXF_BATCH_NO_AUTOTUNE) || params->max_leaf >= 1,
                         AXF_ERR_INVALID_ARGUMENT, "max_leaf must be >= 1 without the autotuner");
         }
@@ -519,24 +540,25 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
         b->p = *params;
         b->probs.assign(problems, problems + nprob);
         const bool tune = !(params->flags & AXF_BATCH_NO_AUTOTUNE);
-        // tile width: given, or the one whose probe S2L ran fastest
-        Rates rates;
+        // the width of problems that name none and are not autotuned: the
+        // flag's, else (autotuner on) the one whose probe S2L ran fastest
+        Rates rates[3];
+        auto rates_of = [&](int t) -> const Rates & {
+            if (rates[t].s2l_unit <= 0) rates[t] = measured_rates(params->order, params->n_modes, kTiles[t], st);
+            return rates[t];
+        };
         if (tb_given) {
             b->tb = tb_given;
         } else if (!tune) {
             b->tb = kDefaultTile;
         } else {
             double best = INFINITY;
-            for (int tb : {2, 4, 8}) {
-                Rates r = measured_rates(params->order, params->n_modes, tb, st);
-                if (r.s2l_seconds < best) {
-                    best = r.s2l_seconds;
-                    b->tb = tb;
-                    rates = r;
+            for (int t = 0; t < 3; ++t)
+                if (rates_of(t).s2l_seconds < best) {
+                    best = rates[t].s2l_seconds;
+                    b->tb = kTiles[t];
                 }
-            }
         }
-        if (tune && tb_given) rates = measured_rates(params->order, params->n_modes, b->tb, st);
         AXF_HIP(hipStreamCreateWithFlags(&b->side.stream, hipStreamNonBlocking));
         AXF_HIP(hipEventCreateWithFlags(&b->side.fork, hipEventDisableTiming));
         AXF_HIP(hipEventCreateWithFlags(&b->side.join, hipEventDisableTiming));
@@ -544,7 +566,8 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             const axf_problem &pb = problems[i];
             axf_params pp = *params;
             pp.nrhs = pb.nrhs;
-            pp.flags = AXF_TILE(b->tb);
+            const int tb_prob = pb.tile ? pb.tile : tb_given;   // 0: not fixed for this problem
+            pp.flags = AXF_TILE(tb_prob ? tb_prob : b->tb);
             Plan *pl = nullptr;
             if (pb.depth != 0 || !tune) {
                 pp.depth = pb.depth;          // 0 without the autotuner: the max_leaf rule
@@ -557,10 +580,15 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
                     throw;
                 }
             } else {
-                pl = tune_problem(pb, pp, rates, b->side, st);
+                // the widths it may take, with their rates
+                Rates cand[3];
+                for (int t = 0; t < 3; ++t)
+                    if (!tb_prob || kTiles[t] == tb_prob) cand[t] = rates_of(t);
+                pl = tune_problem(pb, pp, cand, b->side, st);
             }
             b->plans.push_back(pl);
             b->depth.push_back(pl->d);
+            b->tile.push_back(pl->tb);
         }
         // the batch's passes do not wait on the table stream: tables first
         for (Plan *pl : b->plans)
@@ -572,7 +600,7 @@ axf_status axf_batch_create(const axf_params *params, int32_t nprob, const axf_p
             phiv[i] = problems[i].phi;
         }
         BatchQueues &q = b->q;
-        build_queues(b->plans, Sv, phiv, params->order, params->n_modes, b->tb, b->qmem, q, st);
+        build_queues(b->plans, Sv, phiv, params->order, params->n_modes, b->qmem, q, st);
         // one eager pass (sets kernel attributes), then capture the sequence
         run_batch(q, st, &b->side);
         AXF_HIP(hipStreamSynchronize(st));
@@ -637,11 +665,12 @@ axf_status axf_batch_problem_depth(const axf_batch *b, int32_t i, int32_t *depth
     }
 }
 
-axf_status axf_batch_tile(const axf_batch *b, int32_t *tile)
+axf_status axf_batch_problem_tile(const axf_batch *b, int32_t i, int32_t *tile)
 {
     try {
-        AXF_REQUIRE(b && tile, AXF_ERR_INVALID_ARGUMENT, "batch and tile must be non-NULL");
-        *tile = b->tb;
+        AXF_REQUIRE(b && tile && i >= 0 && i < (int32_t)b->tile.size(), AXF_ERR_INVALID_ARGUMENT,
+                    "bad batch, index or output pointer");
+        *tile = b->tile[i];
         return AXF_OK;
     } catch (const Fail &f) {
         return f.st;

@@ -1349,8 +1349,10 @@ void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
     int dev = 0;
     AXF_HIP(hipGetDevice(&dev));
     allow_lds(kb_s2l<LB, TB, MW, FIX>, shm, dev, attr);
-    int g = std::min(bq.ns2l[l], kPersistBlocks * 2);
-    kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l], bq.ns2l[l], bq.M, bq.nmodes, bq.TS, l);
+    const int t = tile_index(TB);
+    int g = std::min(bq.ns2l[l][t], kPersistBlocks * 2);
+    kb_s2l<LB, TB, MW, FIX><<<g, 64 * s2l_waves(bq.M), shm, st>>>(bq.probs, bq.s2l[l][t], bq.ns2l[l][t], bq.M,
+                                                                   bq.nmodes, bq.TS, l);
 }
 
 template <int NMB, int PART>
@@ -1616,13 +1618,13 @@ void run_batch(const BatchQueues &bq, hipStream_t st, const BatchSide *side)
     for (int l = 2; l <= bq.maxd; ++l) {
         if (bq.nl2l[l])
             kb_l2l<<<std::min(bq.nl2l[l], kPersistBlocks), 256, 0, st>>>(bq.probs, bq.l2l[l], bq.nl2l[l], bq.M, l);
-        if (!bq.ns2l[l]) continue;
 #define AXF_S2L_LAUNCH2(LB, MW, FIX) launch_s2l_batch<LB, 2, MW, FIX>(bq, l, st)
 #define AXF_S2L_LAUNCH4(LB, MW, FIX) launch_s2l_batch<LB, 4, MW, FIX>(bq, l, st)
 #define AXF_S2L_LAUNCH8(LB, MW, FIX) launch_s2l_batch<LB, 8, MW, FIX>(bq, l, st)
-        if (bq.tb == 2) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH2);
-        else if (bq.tb == 8) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH8);
-        else AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH4);
+        // one launch per tile width in use (the problems of a batch may differ)
+        if (bq.ns2l[l][0]) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH2);
+        if (bq.ns2l[l][1]) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH4);
+        if (bq.ns2l[l][2]) AXF_S2L_SHAPES(bq.M, AXF_S2L_LAUNCH8);
 #undef AXF_S2L_LAUNCH2
 #undef AXF_S2L_LAUNCH4
 #undef AXF_S2L_LAUNCH8

@@ -119,6 +119,8 @@ inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
 // comes from params.flags (AXF_TILE_SHIFT), 0 meaning kDefaultTile.
 constexpr int kDefaultTile = 4;
 inline bool s2l_tile_ok(int tb) { return tb == 2 || tb == 4 || tb == 8; }
+constexpr int kTiles[3] = {2, 4, 8};
+inline int tile_index(int tb) { return tb == 2 ? 0 : tb == 4 ? 1 : 2; }
 // P2M work items per leaf: one per pair of channels (the pair shares the
 // sources' offset powers).
 __host__ __device__ inline int p2m_pairs(int C) { return (C + 1) / 2; }
@@ -316,9 +318,12 @@ struct BatchQueues {
     const ProbDev *probs = nullptr;
     int2 *gather = nullptr, *p2m = nullptr, *leaf = nullptr;
     int ngather = 0, np2m = 0, nleaf = 0;
-    int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *s2l[AXF_MAX_DEPTH + 1] = {}, *l2l[AXF_MAX_DEPTH + 1] = {};
-    int nm2m[AXF_MAX_DEPTH + 1] = {}, ns2l[AXF_MAX_DEPTH + 1] = {}, nl2l[AXF_MAX_DEPTH + 1] = {};
-    int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2, tb = kDefaultTile;
+    int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *l2l[AXF_MAX_DEPTH + 1] = {};
+    int nm2m[AXF_MAX_DEPTH + 1] = {}, nl2l[AXF_MAX_DEPTH + 1] = {};
+    // S2L tiles of level l of the problems whose tile width is kTiles[t]
+    int2 *s2l[AXF_MAX_DEPTH + 1][3] = {};
+    int ns2l[AXF_MAX_DEPTH + 1][3] = {};
+    int M = 0, nmodes = 1, nmb = 4, TS = 1, maxd = 2;
     double chistar = 1e300;
 };
 void fill_probdev(const Plan &pl, const double *S, double *phi, ProbDev &pd);

@@ -1,7 +1,8 @@
 """Batched evaluation on the GPU (marked gpu).
 
   * a small batch of uneven problems (one ring, distinct source and field
-    sets, fixed and autotuned depths, 1..8 right-hand sides): the captured
+    sets, fixed and autotuned depths, 1..8 right-hand sides, the three S2L
+    tile widths side by side): the captured
     graph against the oracle FMM of each problem at the depth the batch chose;
   * graph replays with eager work in between (new strengths written in place
     by torch), every replay checked against the plain per-problem launches;
@@ -28,13 +29,15 @@ def _axf():
 
 def _small_problems(nmodes):
     probs = []
-    spec = [(300, 1, 0), (1200, 3, 0), (1, 1, 0), (2500, 2, 4), (700, 8, 0), (60, 1, 3)]
-    for i, (n, q, depth) in enumerate(spec):
+    # (points, right-hand sides, depth, S2L tile width): fixed and autotuned
+    # depths, the three widths side by side in one batch
+    spec = [(300, 1, 0, 2), (1200, 3, 0, 8), (1, 1, 0, 0), (2500, 2, 4, 2), (700, 8, 0, 4), (60, 1, 3, 8)]
+    for i, (n, q, depth, tb) in enumerate(spec):
         r, z, S = inputs.ring_box(n, nmodes, nrhs=q, seed=100 + i)
-        probs.append((r, z, r, z, S, depth))
+        probs.append((r, z, r, z, S, depth, tb))
     # distinct source and field sets
     rs, zs, rf, zf, S = inputs.annulus(900, 400, nmodes, nrhs=2, seed=7)
-    probs.append((rs, zs, rf, zf, S, 0))
+    probs.append((rs, zs, rf, zf, S, 0, 0))
     return probs
 
 
@@ -45,11 +48,12 @@ def test_batch_small_vs_oracle():
     nmodes, M = 5, 8
     probs = _small_problems(nmodes)
     b = axf.Batch(probs, nmodes, M)
-    depths = b.depths()
-    print("depths", depths)
+    depths, tiles = b.depths(), b.tiles()
+    print("depths", depths, "tiles", tiles)
     assert depths[3] == 4 and depths[5] == 3
+    assert [t for t, pb in zip(tiles, probs) if pb[6]] == [pb[6] for pb in probs if pb[6]]
     outs = [to_np(t) for t in b.launch()]
-    for (rs, zs, rf, zf, S, _), d, phi in zip(probs, depths, outs):
+    for (rs, zs, rf, zf, S, _, _), d, phi in zip(probs, depths, outs):
         ref = O.fmm(rs, zs, rf, zf, S, M, d)
         e = rel_err(phi, ref)
         assert np.all(np.isfinite(phi))
@@ -136,6 +140,8 @@ def test_batch_rejects_bad_arguments():
         axf.Batch([(r, z, r, z, S, 15)], 3, 4)       # depth beyond the maximum
     with pytest.raises(axf.AxfError):
         axf.Batch([(r, z, r, z, S)], 3, 30)          # order beyond the maximum
+    with pytest.raises(axf.AxfError):
+        axf.Batch([(r, z, r, z, S, 3, 6)], 3, 4)     # no such S2L tile width
 
 
 
@@ -166,8 +172,8 @@ def test_batch_autotuner_near_best():
         r, z, S = inputs.ring_box(n, nmodes, nrhs=q, seed=300 + i)
         probs.append((r, z, r, z, S))
     b = axf.Batch(probs, nmodes, M)
-    depths, tile = b.depths(), b.tile()
-    print("chosen depths", depths, "tile", tile, flush=True)
+    depths, tiles = b.depths(), b.tiles()
+    print("chosen depths", depths, "tiles", tiles, flush=True)
     b.close()
     for i, pb in enumerate(probs):
         times = {}
@@ -180,7 +186,7 @@ def test_batch_autotuner_near_best():
                 times[(d, tb)] = _median_ms(one.launch)
                 one.close()
         best = min(times.values())
-        chosen = times[(depths[i], tile)]
+        chosen = times[(depths[i], tiles[i])]
         print("problem", i, "times", {k: round(v, 3) for k, v in times.items()}, flush=True)
         assert chosen <= 1.10 * best, (i, chosen, best)
     # the tuned batch still computes the FMM
