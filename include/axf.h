@@ -82,6 +82,7 @@ typedef enum {
 #define AXF_TILE_MASK (0xFu << AXF_TILE_SHIFT)
 #define AXF_TILE(tb) ((uint32_t)(tb) << AXF_TILE_SHIFT)
 #define AXF_NO_OVERLAP (1u << 12)
+#define AXF_S2L_MFMA (1u << 13)
 
 typedef struct {
     int32_t n_modes;

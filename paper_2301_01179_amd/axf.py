@@ -32,6 +32,7 @@ EXPORTED = [
 
 TILE_SHIFT = 8          # AXF_TILE(tb): S2L tile width in params.flags
 NO_OVERLAP = 1 << 12    # AXF_NO_OVERLAP
+S2L_MFMA = 1 << 13      # AXF_S2L_MFMA
 
 PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l", "l2p"]
 
@@ -186,7 +187,7 @@ class Plan:
 
     def __init__(self, r_src, z_src, r_fld, z_fld, n_modes: int, order: int, depth: int = 0,
                  max_leaf: int = 64, nrhs: int = 1, device=None, torch_workspace: bool = False,
-                 tile: int = 0, overlap: bool = True):
+                 tile: int = 0, overlap: bool = True, mfma: bool = False):
         lib = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -194,7 +195,8 @@ class Plan:
         rf, zf = _coords(r_fld, dev), _coords(z_fld, dev)
         self.ns, self.nf = rs.numel(), rf.numel()
         self.n_modes, self.order, self.nrhs = n_modes, order, nrhs
-        p = Params(n_modes, order, depth, max_leaf, nrhs, (tile << TILE_SHIFT) | (0 if overlap else NO_OVERLAP))
+        p = Params(n_modes, order, depth, max_leaf, nrhs,
+                   (tile << TILE_SHIFT) | (0 if overlap else NO_OVERLAP) | (S2L_MFMA if mfma else 0))
         h = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
         with torch.cuda.device(dev):

@@ -164,7 +164,7 @@ static void validate_params(const axf_params *p)
     AXF_REQUIRE(p->depth != 0 || p->max_leaf >= 1, AXF_ERR_INVALID_ARGUMENT,
                 "max_leaf must be >= 1 when depth is 0");
     AXF_REQUIRE(p->nrhs >= 1 && p->nrhs <= AXF_MAX_RHS, AXF_ERR_UNSUPPORTED, "nrhs must be in 1..8");
-    AXF_REQUIRE((p->flags & ~(AXF_TILE_MASK | AXF_NO_OVERLAP)) == 0, AXF_ERR_INVALID_ARGUMENT, "unknown plan flags");
+    AXF_REQUIRE((p->flags & ~(AXF_TILE_MASK | AXF_NO_OVERLAP | AXF_S2L_MFMA)) == 0, AXF_ERR_INVALID_ARGUMENT, "unknown plan flags");
     const int tb = (int)((p->flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
     AXF_REQUIRE(tb == 0 || s2l_tile_ok(tb), AXF_ERR_UNSUPPORTED, "S2L tile width must be 2, 4 or 8 (or 0)");
 }
@@ -199,6 +199,9 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     {
         const int tb = (int)((p.flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
         pl.tb = tb ? tb : kDefaultTile;
+        pl.mfma = (p.flags & AXF_S2L_MFMA) != 0;
+        // matrix-core tiles: 16 boxes (two column tiles) unless AXF_TILE(8)
+        if (pl.mfma) pl.tb = tb == kS2lMfmaBoxes ? kS2lMfmaBoxes : 2 * kS2lMfmaBoxes;
     }
     pl.overlap = !(p.flags & AXF_NO_OVERLAP);
     pl.Cs = pl.nmb * p.nrhs;
@@ -258,9 +261,12 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     // offset groups of the S2L pass and their partial-sum buffer (one level
     // at a time, either side as targets)
     size_t part = 0;
+    int mfma_tpw = 0, mfma_waves = 0;
+    s2l_mfma_shape(pl.M, mfma_tpw, mfma_waves);
     for (Side *sd : {&pl.src, &pl.fld})
         for (int l = 2; l <= d; ++l) {
-            sd->s2l_groups[l] = s2l_group_count(sd->ntiles[l], pl.C, pl.M);
+            sd->s2l_groups[l] =
+                s2l_group_count(sd->ntiles[l], pl.C, pl.M, pl.mfma ? mfma_waves : s2l_waves(pl.M));
             if (sd->s2l_groups[l] > 1)
                 part = std::max(part, (size_t)sd->s2l_groups[l] * sd->nocc[l] * pl.C * pl.P);
         }

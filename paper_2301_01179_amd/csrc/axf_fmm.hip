@@ -540,6 +540,320 @@ __device__ __forceinline__ void s2l_tile_body(int M, int nmodes, int nrhs, int l
     }
 }
 
+// ------------------------------------------------------- S2L, matrix cores
+// The units of the tiled form contracted on the FP64 matrix cores
+// (v_mfma_f64_16x16x4): for one (tile of up to 8 boxes, channel) and one
+// unit, Out[(k, l)][col] += sum over (i, j) of T[k][i][j + l] X[(i, j)][col]
+// (T[i][k][j + l] for an inward unit), the 16 columns being the real and
+// imaginary parts of the 8 boxes' combined moments (A for even l, B for odd
+// l).  Output rows are split by the parity of l, k-major, in tiles of 16;
+// wave w keeps the row tiles w, w + 4, ... as 16 x 16 blocks in registers
+// through every unit.  A k-step takes 4 consecutive packed moments (i, j):
+// each lane gathers its operand T entry of every row tile (16 rows x 4
+// columns of a Hankel block: a few cache lines) and its box's two moments
+// straight from memory, one step ahead of the matrix cores, and forms the
+// combined moments in registers; no LDS staging, no barriers.  Padded rows
+// read row (0, 0), padded columns column (M, 0) (valid table entries) and
+// meet zero moments or are not written.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int TPW, int NB>
+__device__ __forceinline__ void s2l_mfma_body(int M, int nmodes, int nrhs, int level,
+                                              const int4 *__restrict__ tiles, const int32_t *__restrict__ tslots,
+                                              const int32_t *__restrict__ tbox, const int32_t *__restrict__ sslot,
+                                              const double2 *__restrict__ mom, const double *__restrict__ tab,
+                                              double2 *__restrict__ loc, int item, int G, double2 *__restrict__ part,
+                                              int nocc, double tscale, int TS, int W)
+{
+    constexpr int TB = kS2lMfmaBoxes * NB;   // NB column tiles of 8 boxes
+    __shared__ double invfact[AXF_MAX_ORDER + 1];
+    // the block's units: table offset, orientation, source slots per box
+    __shared__ int64_t u_toff[18];
+    __shared__ int u_out[18];
+    __shared__ int u_src[18][2][TB];
+    __shared__ int s_nunits;
+    const int P = (M + 1) * (M + 2) / 2;
+    const int C = nmodes * nrhs;
+    // work item: (tile, channel, offset group, row group w of W); the W
+    // one-wave blocks of a (tile, channel, group) are neighbours
+    const int w = item % W;
+    item /= W;
+    const int ti = item / (C * G), rem = item - ti * (C * G);
+    const int c = rem / G, g = rem - (rem / G) * G;
+    const int n = c / nrhs;
+    const int4 tl = tiles[ti];
+    const int station = tl.x, nbx = tl.w;
+    const int nb = 1 << level;
+    const int tid = threadIdx.x, lane = tid;
+
+    if (tid <= M) {
+        double f = 1.0;
+        for (int t = 2; t <= tid; ++t) f *= t;
+        invfact[tid] = 1.0 / f;
+    }
+    // unit list (thread b < TB resolves the sources of box b; thread 0 also
+    // the tables), in the order of the interaction list, this group's share
+    if (tid < TB) {
+        const int b = tid;
+        const int sl = b < nbx ? tslots[tl.z + b] : -1;
+        const int bid = sl >= 0 ? tbox[sl] : 0;
+        const int zb = bid - (bid / nb) * nb;
+        const int dr0 = -2 - (station & 1), dz0 = -2 - tl.y;
+        int oc = 0, nu = 0;
+        for (int dr = dr0; dr < dr0 + 6; ++dr) {
+            const int jr = station + dr;
+            const bool near_r = dr >= -1 && dr <= 1;
+            for (int adz = 0; adz <= 3; ++adz) {
+                const bool hasp = adz > 0 && adz <= dz0 + 5 && !(near_r && adz <= 1);
+                const bool hasm = -adz >= dz0 && !(near_r && adz <= 1);
+                if (!hasp && !hasm) continue;
+                if (oc++ % G != g || jr < 0 || jr >= nb) continue;
+                const int jp = zb + adz, jm = zb - adz;
+                u_src[nu][0][b] = (hasp && sl >= 0 && jp < nb) ? sslot[jr * nb + jp] : -1;
+                u_src[nu][1][b] = (hasm && sl >= 0 && jm >= 0) ? sslot[jr * nb + jm] : -1;
+                if (b == 0) {
+                    const bool outward = dr <= 0;
+                    const int inner = outward ? jr : station;
+                    const int adr = outward ? -dr : dr;
+                    u_toff[nu] = (int64_t)n * TS + ((int64_t)inner * 12 + geom_slot(adr, adz)) * nmodes * TS;
+                    u_out[nu] = outward;
+                }
+                ++nu;
+            }
+        }
+        if (b == 0) s_nunits = nu;
+    }
+    __syncthreads();
+    if (tid == 0) {                             // drop the units no box of the tile has sources for
+        int m = 0;
+        for (int u = 0; u < s_nunits; ++u) {
+            bool any = false;
+            for (int b = 0; b < TB; ++b) any |= u_src[u][0][b] >= 0 || u_src[u][1][b] >= 0;
+            if (!any) continue;
+            if (m != u) {
+                u_toff[m] = u_toff[u];
+                u_out[m] = u_out[u];
+                for (int b = 0; b < TB; ++b) {
+                    u_src[m][0][b] = u_src[u][0][b];
+                    u_src[m][1][b] = u_src[u][1][b];
+                }
+            }
+            ++m;
+        }
+        s_nunits = m;
+    }
+    // rows of each parity and their tiles
+    int R0 = 0, R1 = 0;
+    for (int k = 0; k <= M; ++k) {
+        R0 += (M + 2 - k) / 2;
+        R1 += (M + 1 - k) / 2;
+    }
+    const int NT0 = (R0 + 15) / 16, NT = NT0 + (R1 + 15) / 16;
+    // the table position of this lane's operand row (k, l) of each row tile,
+    // for both orientations: entry (a, b, c) sits at table_row(M, a, b) + c,
+    // so row (k, l) meets column (i, j) at
+    //   outward  table_row(M, k, i) + j + l = ro + i (2M + 1 - k) + j - i (i - 1) / 2
+    //   inward   table_row(M, i, k) + j + l = ri - i k + table_row(M, i, 0) + j
+    const int K2 = 2 * M + 1;
+    int ro[TPW], ri[TPW], kr[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = w + W * u;
+        int k = 0, l = 0;
+        if (t < NT) {
+            const int par = t >= NT0;
+            int idx = (par ? t - NT0 : t) * 16 + (lane & 15);
+            if (idx < (par ? R1 : R0)) {
+                for (;; ++k) {
+                    const int cnt = (M + 1 - k + 1 - par) / 2;
+                    if (idx < cnt) break;
+                    idx -= cnt;
+                }
+                l = par + 2 * idx;
+            }
+        }
+        kr[u] = k;
+        ro[u] = table_row(M, k, 0) + l;
+        ri[u] = k * K2 - (k * (k - 1)) / 2 + l;
+    }
+    mfma_d4 acc[TPW][NB];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u)
+#pragma unroll
+        for (int h = 0; h < NB; ++h) acc[u][h] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();                            // unit list, invfact
+
+    const int kk = lane >> 4;                   // this lane's column of the 4 x 16 moment block
+    const int col = lane & 15, mb = col >> 1, comp = col & 1;
+    const int nst = (P + 3) >> 2;
+    const double *dmom = reinterpret_cast<const double *>(mom);
+    const int nunits = s_nunits;
+    for (int un = 0; un < nunits; ++un) {
+        // the unit's table (uniform: its entries are addressed by 32-bit byte
+        // offsets from a scalar base; a table is (M + 1)^3 doubles)
+        const int64_t toff = u_toff[un];
+        const uint32_t tlo = __builtin_amdgcn_readfirstlane((uint32_t)toff);
+        const uint32_t thi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)toff >> 32));
+        const char *Tb = reinterpret_cast<const char *>(tab + (int64_t)(((uint64_t)thi << 32) | tlo));
+        const bool outward = u_out[un] != 0;
+        int base[TPW], mult[TPW];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            base[u] = outward ? ro[u] : ri[u];
+            mult[u] = outward ? K2 - kr[u] : -kr[u];
+        }
+        // this lane's box of each column tile (mb + 8 h)
+        const double *mp[NB], *mm[NB];
+        double fp[NB], fm[NB];
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            const int sp = u_src[un][0][mb + 8 * h], sm = u_src[un][1][mb + 8 * h];
+            const bool hasp = sp >= 0, hasm = sm >= 0;
+            // a box without a source reads the moments of slot 0 (valid) and drops them
+            mp[h] = dmom + 2 * ((int64_t)(hasp ? sp : 0) * C + c) * P + comp;
+            mm[h] = dmom + 2 * ((int64_t)(hasm ? sm : 0) * C + c) * P + comp;
+            fp[h] = hasp ? 1.0 : 0.0;
+            fm[h] = hasm ? 1.0 : 0.0;
+        }
+        // operands of the k-step holding packed moment p = (i, j) in this
+        // lane's column; every load is unconditional and in bounds (a column
+        // past the last moment reads (M, 0) and moment P - 1, then drops them)
+        // (the moments are taken raw and scaled by 0 or 1 where they are
+        // used, so that no branch or select waits on the load)
+        auto gather = [&](int p, int i, int j, double (&av)[TPW], double (&xp)[NB], double (&xm)[NB]) {
+            const bool live = p < P;
+            const int ii = live ? i : M, jj = live ? j : 0;
+            const int cterm = outward ? jj - (ii * (ii - 1)) / 2 : table_row(M, ii, 0) + jj;
+#pragma unroll
+            for (int u = 0; u < TPW; ++u)
+                av[u] = *reinterpret_cast<const double *>(Tb + (uint32_t)(base[u] + ii * mult[u] + cterm) * 8u);
+            const int pc = live ? p : P - 1;
+#pragma unroll
+            for (int h = 0; h < NB; ++h) {
+                xp[h] = mp[h][2 * pc];
+                xm[h] = mm[h][2 * pc];
+            }
+        };
+        // (i, j) of packed index p + 4 from (i, j) of p (past the last moment
+        // i runs to M + 1, which gather clamps)
+        auto advance = [&](int &i, int &j) {
+            j += 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {       // rows are >= 1 long: at most 4 wraps
+                const bool wrap = i <= M && j > M - i;
+                j = wrap ? j - (M + 1 - i) : j;
+                i = wrap ? i + 1 : i;
+            }
+        };
+        // the contraction of one k-step: operands av, raw moments (xp, xm)
+        // of column (p, j)
+        auto contract = [&](const double (&av)[TPW], const double (&xp)[NB], const double (&xm)[NB], int p, int j) {
+            // combined moments: A = M+ + (-1)^j M-, B = M+ - (-1)^j M-
+            const double live = p < P ? 1.0 : 0.0;
+            double bA[NB], bB[NB];
+#pragma unroll
+            for (int h = 0; h < NB; ++h) {
+                const double vp = xp[h] * (fp[h] * live), vm = xm[h] * (((j & 1) ? -fm[h] : fm[h]) * live);
+                bA[h] = vp + vm;
+                bB[h] = vp - vm;
+            }
+            // every tile of the wave runs (an idle tile's rows read row
+            // (0, 0) and are never written), so no branch splits the step;
+            // each operand block feeds the NB column tiles
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                const int t = w + W * u;
+#pragma unroll
+                for (int h = 0; h < NB; ++h)
+                    acc[u][h] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], t >= NT0 ? bB[h] : bA[h], acc[u][h], 0, 0, 0);
+            }
+        };
+        // two operand sets used in turn: the loads of step st + 1 go to the
+        // other set while the matrix cores run step st (no register copies,
+        // so nothing waits on a load before its step)
+        int p0 = kk, i0 = 0, j0 = kk;
+        while (j0 > M - i0 && i0 < M) {         // (i, j) of p = kk
+            j0 -= M + 1 - i0;
+            ++i0;
+        }
+        double a0[TPW], a1[TPW], x0p[NB], x0m[NB], x1p[NB], x1m[NB];
+        gather(p0, i0, j0, a0, x0p, x0m);
+        // (the loop body is one branch-free block, the step count rounded up
+        // to even (a step past the last moment adds zeros), and the
+        // scheduling barriers keep each step's loads ahead of the other
+        // set's matrix operations)
+        for (int st = 0; st < nst; st += 2) {
+            int p1 = p0 + 4, i1 = i0, j1 = j0;
+            advance(i1, j1);
+            gather(p1, i1, j1, a1, x1p, x1m);
+            __builtin_amdgcn_sched_barrier(0);
+            contract(a0, x0p, x0m, p0, j0);
+            __builtin_amdgcn_sched_barrier(0);
+            p0 = p1 + 4;
+            i0 = i1;
+            j0 = j1;
+            advance(i0, j0);
+            gather(p0, i0, j0, a0, x0p, x0m);
+            __builtin_amdgcn_sched_barrier(0);
+            contract(a1, x1p, x1m, p1, j1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // lane holds rows lane / 16 + 4 v, v < 4, of column lane % 16 of each of
+    // its row tiles; (-1)^l / l! times the sum goes to the locals (or this
+    // group's partial sums)
+    double *dl = reinterpret_cast<double *>(loc);
+    double *dp = reinterpret_cast<double *>(part);
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
+    const int ob = mb + 8 * h;
+    if (ob >= nbx) break;
+    const int slot = tslots[tl.z + ob];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int t = w + W * u;
+        if (t >= NT) continue;
+        const int par = t >= NT0;
+        const int Rp = par ? R1 : R0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int idx = (par ? t - NT0 : t) * 16 + (lane >> 4) + 4 * v;
+            if (idx >= Rp) continue;
+            int k = 0;
+            for (;; ++k) {
+                const int cnt = (M + 1 - k + 1 - par) / 2;
+                if (idx < cnt) break;
+                idx -= cnt;
+            }
+            const int ll = par + 2 * idx;
+            const double f = ((ll & 1) ? -tscale : tscale) * invfact[ll];
+            const int64_t e = ((int64_t)slot * C + c) * P + tri_index(M, k, ll);
+            if (part) {
+                dp[2 * ((int64_t)g * nocc * C * P + e) + comp] = f * acc[u][h][v];
+            } else {
+                dl[2 * e + comp] = fma(f, acc[u][h][v], dl[2 * e + comp]);
+            }
+        }
+    }
+    }
+}
+
+template <int TPW, int NB>
+__global__ __launch_bounds__(64) void k_s2l_mfma(int M, int nmodes, int nrhs, int level, int TS,
+                                                             const int4 *__restrict__ tiles,
+                                                             const int32_t *__restrict__ tslots,
+                                                             const int32_t *__restrict__ tbox,
+                                                             const int32_t *__restrict__ sslot,
+                                                             const double2 *__restrict__ mom,
+                                                             const double *__restrict__ tab, double2 *__restrict__ loc,
+                                                             int G, double2 *__restrict__ part, int nocc, double tscale,
+                                                             int W)
+{
+    s2l_mfma_body<TPW, NB>(M, nmodes, nrhs, level, tiles, tslots, tbox, sslot, mom, tab, loc, blockIdx.x, G, part, nocc,
+                           tscale, TS, W);
+}
+
 // Sum of the offset groups' partial S2L results into the locals, in group
 // order (deterministic).
 __global__ __launch_bounds__(256) void k_s2l_reduce(int64_t n, int G, const double2 *__restrict__ part,
@@ -1157,6 +1471,37 @@ void launch_s2l_t(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t
     }
 }
 
+void launch_s2l_mfma(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
+{
+    const int G = tgt.s2l_groups[l];
+    double2 *part = G > 1 ? pl.s2l_part : nullptr;
+    int tpw = 0, waves = 0;
+    s2l_mfma_shape(pl.M, tpw, waves);
+    // two column tiles (16 boxes) where a station's column parity holds
+    // more than 8 boxes, else one
+    const bool two = (1 << (l - 1)) > kS2lMfmaBoxes && pl.tb > kS2lMfmaBoxes;
+#define AXF_S2L_MFMA(T, NB)                                                                                      \
+    k_s2l_mfma<T, NB><<<tgt.ntiles[l] * pl.C * G * waves, 64, 0, st>>>(                                          \
+        pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],          \
+        pl.lev[l].mom, pl.lev[l].tab, pl.lev[l].loc, G, part, tgt.nocc[l], pl.lev[l].tscale, waves)
+    if (two) {
+        if (tpw == 4) AXF_S2L_MFMA(4, 2);
+        else if (tpw == 5) AXF_S2L_MFMA(5, 2);
+        else if (tpw == 6) AXF_S2L_MFMA(6, 2);
+        else AXF_S2L_MFMA(7, 2);
+    } else {
+        if (tpw == 4) AXF_S2L_MFMA(4, 1);
+        else if (tpw == 5) AXF_S2L_MFMA(5, 1);
+        else if (tpw == 6) AXF_S2L_MFMA(6, 1);
+        else AXF_S2L_MFMA(7, 1);
+    }
+#undef AXF_S2L_MFMA
+    if (G > 1) {
+        const int64_t n = (int64_t)tgt.nocc[l] * pl.C * pl.P;
+        k_s2l_reduce<<<(int)((n + 255) / 256), 256, 0, st>>>(n, G, part, pl.lev[l].loc);
+    }
+}
+
 void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t st)
 {
     {
@@ -1166,6 +1511,10 @@ void launch_s2l(Plan &pl, const Side &src, const Side &tgt, int l, hipStream_t s
                                                    l > 2 ? pl.lev[l - 1].loc : nullptr, pl.lev[l].loc, pl.shift_coef);
     }
     PhaseTimer tm(pl, st, AXF_PHASE_S2L);
+    if (pl.mfma) {
+        launch_s2l_mfma(pl, src, tgt, l, st);
+        return;
+    }
 #define AXF_S2L_LAUNCH2(LB, MW, FIX) launch_s2l_t<LB, 2, MW, FIX>(pl, src, tgt, l, st)
 #define AXF_S2L_LAUNCH4(LB, MW, FIX) launch_s2l_t<LB, 4, MW, FIX>(pl, src, tgt, l, st)
 #define AXF_S2L_LAUNCH8(LB, MW, FIX) launch_s2l_t<LB, 8, MW, FIX>(pl, src, tgt, l, st)

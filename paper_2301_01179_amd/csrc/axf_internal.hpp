@@ -121,6 +121,34 @@ constexpr int kDefaultTile = 4;
 inline bool s2l_tile_ok(int tb) { return tb == 2 || tb == 4 || tb == 8; }
 constexpr int kTiles[3] = {2, 4, 8};
 inline int tile_index(int tb) { return tb == 2 ? 0 : tb == 4 ? 1 : 2; }
+// Matrix-core S2L: tiles of 8 boxes (16 real columns); the outputs of a
+// (box, channel) in row tiles of 16 (rows of one column parity), at most 21
+// for M <= 24, dealt to W <= 4 waves of TPW tiles each (4 <= TPW <= 7), the
+// pair that leaves the fewest idle tiles (ties: more tiles per wave).
+constexpr int kS2lMfmaBoxes = 8;
+inline int s2l_row_tiles(int M)
+{
+    int r0 = 0, r1 = 0;
+    for (int k = 0; k <= M; ++k) {
+        r0 += (M + 2 - k) / 2;
+        r1 += (M + 1 - k) / 2;
+    }
+    return (r0 + 15) / 16 + (r1 + 15) / 16;
+}
+inline void s2l_mfma_shape(int M, int &tpw, int &waves)
+{
+    const int nt = s2l_row_tiles(M);
+    int best = 1 << 30;
+    for (int t = 7; t >= 4; --t) {
+        const int w = (nt + t - 1) / t;
+        if (w > 4) continue;
+        if (w * t - nt < best) {
+            best = w * t - nt;
+            tpw = t;
+            waves = w;
+        }
+    }
+}
 // P2M work items per leaf: one per pair of channels (the pair shares the
 // sources' offset powers).
 __host__ __device__ inline int p2m_pairs(int C) { return (C + 1) / 2; }
@@ -132,9 +160,9 @@ constexpr size_t kTablePad = 64;
 // Offset groups of a level: the 18 offset units (pairs (dr, +-dz) of the
 // interaction list) of a (tile, channel) are split over G blocks so that a
 // level launches ~2048 waves.
-inline int s2l_group_count(int ntiles, int C, int M)
+inline int s2l_group_count(int ntiles, int C, int M, int waves_per_block)
 {
-    const int64_t waves = (int64_t)ntiles * C * s2l_waves(M);
+    const int64_t waves = (int64_t)ntiles * C * waves_per_block;
     if (waves <= 0) return 1;
     int64_t g = (2048 + waves - 1) / waves;
     return (int)(g < 1 ? 1 : g > 9 ? 9 : g);
@@ -165,6 +193,7 @@ struct Plan {
     int N = 0, M = 0, P = 0, C = 0, TS = 0, d = 0, nrhs = 1, nmodes = 1;
     int nmb = 4, Cs = 4;        // mode bucket and padded channels per point in Sg
     int tb = kDefaultTile;      // S2L tile width (target boxes per tile)
+    bool mfma = false;          // S2L on the matrix cores (tiles of kS2lMfmaBoxes)
     bool overlap = true;        // near field beside the downward pass (second stream)
     double rlo = 0, zlo = 0, L = 1, invL = 1;
     double rmax = 0;                     // largest ring radius of both sets

@@ -38,10 +38,10 @@ def test_invalid_geometry(bad):
     assert ei.value.status == 2
 
 
-def _check(r, z, rf, zf, S, M, depth, tol=TOL, tile=0):
+def _check(r, z, rf, zf, S, M, depth, tol=TOL, tile=0, mfma=False):
     axf = _axf()
     nrhs, nm, _ = S.shape
-    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs, tile=tile)
+    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs, tile=tile, mfma=mfma)
     d = plan.info()["depth"]
     phi = to_np(plan.evaluate(torch.from_numpy(S)))
     ref = O.fmm(r, z, rf, zf, S, M, d)
@@ -111,6 +111,24 @@ def test_tile_widths(tile, M):
     need_gpu()
     r, z, S = inputs.ring_box(900, 3, nrhs=2, seed=400 + M + tile)
     _check(r, z, r, z, S, M, 4, tile=tile)
+
+
+@gpu
+@pytest.mark.parametrize("M,depth,tile", [(0, 4, 0), (1, 4, 0), (2, 4, 0), (3, 4, 0), (5, 4, 0), (7, 4, 0),
+                                          (10, 4, 0), (11, 4, 0), (12, 4, 0), (14, 4, 0), (17, 4, 0), (19, 4, 0),
+                                          (22, 4, 0), (24, 4, 0), (6, 5, 0), (12, 5, 0), (15, 5, 0), (16, 5, 0),
+                                          (20, 5, 0), (23, 5, 0), (24, 5, 0), (24, 5, 8), (9, 6, 0)])
+def test_s2l_matrix_cores(M, depth, tile):
+    """The S2L pass on the FP64 matrix cores: output row tiles of 16 split by
+    column parity, dealt to 1..4 waves of 4..7 tiles (every shape the orders
+    0..24 choose), one column tile of 8 boxes up to level 4 and two (16
+    boxes) from level 5 (tile 8: one everywhere); depth 4 runs levels whose
+    units are split over offset groups (partial sums) and levels written
+    directly."""
+    need_gpu()
+    n = {4: 900, 5: 2500, 6: 6000}[depth]
+    r, z, S = inputs.ring_box(n, 3, nrhs=2, seed=500 + M + depth)
+    _check(r, z, r, z, S, M, depth, tile=tile, mfma=True)
 
 
 @gpu
