@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--order", type=int, default=HEADLINE_ORDER)
     ap.add_argument("--depth", type=int, default=0, help="0 = autotuned (with the tile width)")
-    ap.add_argument("--tile", type=int, default=0, help="S2L tile width 2, 4 or 8; 0 = autotuned")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="S2L kernel: 0 = matrix cores (tiles of up to 16 boxes), 2, 4 or 8 = vector units "
+                         "with that tile width; -1 = autotuned")
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--ns", type=int, default=50000)
     ap.add_argument("--nf", type=int, default=50000)
@@ -97,9 +99,10 @@ def read_traffic(phase, kernel_file="axf_fmm.hip"):
         return None
 
 
-def autotune_depth(torch, axf, coords, S, nmodes, order, candidates, tiles=(4,)):
-    """Pick the (depth, S2L tile width) with the shortest plan + evaluate time
-    (the second of two trials each)."""
+def autotune_depth(torch, axf, coords, S, nmodes, order, candidates, tiles=(0,)):
+    """Pick the (depth, S2L kernel) with the shortest plan + evaluate time
+    (the second of two trials each); tile 0 is the matrix-core S2L, 2, 4 and
+    8 the vector-unit one with that tile width."""
     rs, zs, rf, zf = coords
     best = None
     for d in candidates:
@@ -382,8 +385,8 @@ def main():
     depth, tile = args.depth, args.tile
     if depth == 0:
         depth, tile = autotune_depth(torch, axf, coords, S, nm, args.order, [3, 4, 5, 6, 7],
-                                     (2, 4, 8) if tile == 0 else (tile,))
-    tile = tile or 4
+                                     (0, 2, 4, 8) if tile < 0 else (tile,))
+    tile = max(tile, 0)
 
     plan, phi, t_step, t_eval, timing = measure(torch, axf, coords, S, nm, args.order, depth,
                                                 args.steps, args.warmup, tile)
@@ -434,7 +437,10 @@ def main():
     ms_dom, launches = timing[dom]
     achieved = flops[dom] / (ms_dom / 1e3 / args.steps) / 1e12 if ms_dom > 0 else 0.0
     traffic = read_traffic(dom)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+    # the matrix-core S2L is bound by the FP64 MFMA rate (the same 78.6
+    # TFLOP/s on MI355X as the vector FMA rate); everything else by the vector ALU
+    bound = "mfma" if dom == "s2l" and tile == 0 else "alu"
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
                 "traffic": traffic, "kernel": dom,
                 "avg_launch_ms": round(ms_dom / max(launches, 1), 4),
@@ -470,7 +476,7 @@ def main():
 
     secondary = None
     if not args.no_secondary and args.order != CONFIG_ORDER:
-        d2, tb2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7], (2, 4, 8))
+        d2, tb2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7], (0, 2, 4, 8))
         p2, phi2, ts2, te2, _ = measure(torch, axf, coords, S, nm, CONFIG_ORDER, d2,
                                         max(3, args.steps // 2), 1, tb2)
         phi2_s = phi2[..., sample].cpu().numpy()
@@ -511,8 +517,11 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"annulus: {ns} ring sources + {nf} distinct field points, r in [0.1,1], "
                                f"z in [-1,1], modes 0..{nm - 1}, complex N(0,1) strengths",
-                   "order": args.order, "depth": depth, "s2l_tile": tile,
-                   "depth_choice": "fastest of depths 3..7 x S2L tile widths 2, 4, 8 (timed plan + evaluate)"
+                   "order": args.order, "depth": depth,
+                   "s2l_kernel": "matrix cores, tiles of up to 16 boxes" if tile == 0
+                   else f"vector units, tiles of {tile} boxes",
+                   "depth_choice": "fastest of depths 3..7 x S2L kernels (matrix cores; vector units with "
+                                   "tiles of 2, 4, 8) (timed plan + evaluate)"
                    if args.depth == 0 else "given",
                    "max_points_per_leaf": leaf_occupancy(info, coords_np), "nrhs": 1,
                    "step": "plan (tree + tables) + evaluate",

@@ -71,18 +71,20 @@ typedef enum {
  *             max_leaf field points in every leaf (capped at AXF_MAX_DEPTH).
  *   max_leaf: leaf bound used when depth == 0 (>= 1).
  *   nrhs    : right-hand sides sharing the geometry (1..AXF_MAX_RHS).
- *   flags   : AXF_TILE(tb) selects the S2L tile width, the number of
- *             same-parity target boxes of one radial station that share one
- *             table read (section 2.2's operator reuse): 2, 4 or 8; 0 (no
- *             flag) = 4.  AXF_NO_OVERLAP: potential evaluations run the near
- *             field after the downward pass on the caller's stream instead
- *             of beside it on a second stream of the library.  Other bits
- *             must be 0. */
+ *   flags   : the S2L pass contracts, for each interaction-list offset,
+ *             one table per radial station and mode against the moments of
+ *             several target boxes of that station at once (section 2.2's
+ *             operator reuse).  No AXF_TILE flag (the default): on the FP64
+ *             matrix cores, up to 16 boxes of a station column per tile.
+ *             AXF_TILE(tb), tb = 2, 4 or 8: on the vector units, tb
+ *             same-parity boxes per tile.  AXF_NO_OVERLAP: potential
+ *             evaluations run the near field after the downward pass on the
+ *             caller's stream instead of beside it on a second stream of the
+ *             library.  Other bits must be 0. */
 #define AXF_TILE_SHIFT 8
 #define AXF_TILE_MASK (0xFu << AXF_TILE_SHIFT)
 #define AXF_TILE(tb) ((uint32_t)(tb) << AXF_TILE_SHIFT)
 #define AXF_NO_OVERLAP (1u << 12)
-#define AXF_S2L_MFMA (1u << 13)
 
 typedef struct {
     int32_t n_modes;

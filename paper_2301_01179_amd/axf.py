@@ -32,7 +32,6 @@ EXPORTED = [
 
 TILE_SHIFT = 8          # AXF_TILE(tb): S2L tile width in params.flags
 NO_OVERLAP = 1 << 12    # AXF_NO_OVERLAP
-S2L_MFMA = 1 << 13      # AXF_S2L_MFMA
 
 PHASES = ["gather", "p2m", "m2m", "s2l", "leaf", "direct", "l2l", "l2p"]
 
@@ -177,7 +176,9 @@ class Plan:
 
     r_src, z_src, r_fld, z_fld: float64 tensors (or arrays) of ring radii and
     axial stations.  n_modes = N + 1, order = M, depth 0 = automatic with at
-    most max_leaf points per leaf; tile = S2L tile width 2, 4 or 8 (0: 4);
+    most max_leaf points per leaf; tile = 0 runs the S2L pass on the matrix
+    cores (tiles of up to 16 boxes), 2, 4 or 8 on the vector units with that
+    many boxes per tile;
     overlap=False keeps the near field on the caller's stream after the
     downward pass (AXF_NO_OVERLAP).
     torch_workspace=True moves every buffer of
@@ -187,7 +188,7 @@ class Plan:
 
     def __init__(self, r_src, z_src, r_fld, z_fld, n_modes: int, order: int, depth: int = 0,
                  max_leaf: int = 64, nrhs: int = 1, device=None, torch_workspace: bool = False,
-                 tile: int = 0, overlap: bool = True, mfma: bool = False):
+                 tile: int = 0, overlap: bool = True):
         lib = load_library()
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -195,8 +196,7 @@ class Plan:
         rf, zf = _coords(r_fld, dev), _coords(z_fld, dev)
         self.ns, self.nf = rs.numel(), rf.numel()
         self.n_modes, self.order, self.nrhs = n_modes, order, nrhs
-        p = Params(n_modes, order, depth, max_leaf, nrhs,
-                   (tile << TILE_SHIFT) | (0 if overlap else NO_OVERLAP) | (S2L_MFMA if mfma else 0))
+        p = Params(n_modes, order, depth, max_leaf, nrhs, (tile << TILE_SHIFT) | (0 if overlap else NO_OVERLAP))
         h = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
         with torch.cuda.device(dev):

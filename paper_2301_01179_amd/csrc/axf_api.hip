@@ -164,7 +164,7 @@ static void validate_params(const axf_params *p)
     AXF_REQUIRE(p->depth != 0 || p->max_leaf >= 1, AXF_ERR_INVALID_ARGUMENT,
                 "max_leaf must be >= 1 when depth is 0");
     AXF_REQUIRE(p->nrhs >= 1 && p->nrhs <= AXF_MAX_RHS, AXF_ERR_UNSUPPORTED, "nrhs must be in 1..8");
-    AXF_REQUIRE((p->flags & ~(AXF_TILE_MASK | AXF_NO_OVERLAP | AXF_S2L_MFMA)) == 0, AXF_ERR_INVALID_ARGUMENT, "unknown plan flags");
+    AXF_REQUIRE((p->flags & ~(AXF_TILE_MASK | AXF_NO_OVERLAP)) == 0, AXF_ERR_INVALID_ARGUMENT, "unknown plan flags");
     const int tb = (int)((p->flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
     AXF_REQUIRE(tb == 0 || s2l_tile_ok(tb), AXF_ERR_UNSUPPORTED, "S2L tile width must be 2, 4 or 8 (or 0)");
 }
@@ -198,10 +198,10 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     pl.nmb = mode_bucket(p.n_modes);
     {
         const int tb = (int)((p.flags & AXF_TILE_MASK) >> AXF_TILE_SHIFT);
-        pl.tb = tb ? tb : kDefaultTile;
-        pl.mfma = (p.flags & AXF_S2L_MFMA) != 0;
-        // matrix-core tiles: 16 boxes (two column tiles) unless AXF_TILE(8)
-        if (pl.mfma) pl.tb = tb == kS2lMfmaBoxes ? kS2lMfmaBoxes : 2 * kS2lMfmaBoxes;
+        // no tile flag: the matrix-core S2L on tiles of up to 16 boxes (two
+        // column tiles); AXF_TILE(tb): the vector-unit S2L on tb boxes
+        pl.mfma = tb == 0;
+        pl.tb = tb ? tb : 2 * kS2lMfmaBoxes;
     }
     pl.overlap = !(p.flags & AXF_NO_OVERLAP);
     pl.Cs = pl.nmb * p.nrhs;

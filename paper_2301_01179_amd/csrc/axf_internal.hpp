@@ -115,8 +115,9 @@ inline int s2l_slots(int M, int lb)
 }
 inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
-// Tile widths the S2L kernels are compiled for (boxes per tile); a plan's
-// comes from params.flags (AXF_TILE_SHIFT), 0 meaning kDefaultTile.
+// Tile widths the vector-unit S2L kernels are compiled for (boxes per
+// tile), from params.flags (AXF_TILE_SHIFT; 0 there selects the matrix-core
+// kernel); kDefaultTile is the batch kernels' width when none is chosen.
 constexpr int kDefaultTile = 4;
 inline bool s2l_tile_ok(int tb) { return tb == 2 || tb == 4 || tb == 8; }
 constexpr int kTiles[3] = {2, 4, 8};

@@ -38,10 +38,10 @@ def test_invalid_geometry(bad):
     assert ei.value.status == 2
 
 
-def _check(r, z, rf, zf, S, M, depth, tol=TOL, tile=0, mfma=False):
+def _check(r, z, rf, zf, S, M, depth, tol=TOL, tile=0):
     axf = _axf()
     nrhs, nm, _ = S.shape
-    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs, tile=tile, mfma=mfma)
+    plan = axf.Plan(r, z, rf, zf, nm, M, depth=depth, nrhs=nrhs, tile=tile)
     d = plan.info()["depth"]
     phi = to_np(plan.evaluate(torch.from_numpy(S)))
     ref = O.fmm(r, z, rf, zf, S, M, d)
@@ -93,42 +93,52 @@ def test_order_limits(M):
 @gpu
 @pytest.mark.parametrize("M", [17, 20, 21, 22, 23])
 def test_s2l_orders(M):
-    """Orders 17..23 run the remaining compiled S2L shapes: window bound 20
-    with partial rows (17) and with exact rows (20), window bound 24 with one
-    column block per lane (21) and with two, whose windows run past the row
-    ends into the next row or the table padding (22, 23)."""
+    """Orders 17..23 run the remaining compiled vector-unit S2L shapes
+    (tiles of 4): window bound 20 with partial rows (17) and with exact rows
+    (20), window bound 24 with one column block per lane (21) and with two,
+    whose windows run past the row ends into the next row or the table
+    padding (22, 23)."""
     need_gpu()
     r, z, S = inputs.ring_box(400, 3, nrhs=2, seed=170 + M)
-    _check(r, z, r, z, S, M, 3)
+    _check(r, z, r, z, S, M, 3, tile=4)
+
+
+@gpu
+@pytest.mark.parametrize("M", [0, 2, 4, 6, 8, 10, 12, 14, 16])
+def test_vector_s2l_low_orders(M):
+    """The vector-unit S2L (tiles of 4) at orders 0..16: window bounds 4, 8,
+    12 and 16, each with exact rows (M = bound, fully unrolled) and partial
+    rows."""
+    need_gpu()
+    r, z, S = inputs.ring_box(500, 3, nrhs=2, seed=700 + M)
+    _check(r, z, r, z, S, M, 3, tile=4)
 
 
 @gpu
 @pytest.mark.parametrize("tile", [2, 8])
 @pytest.mark.parametrize("M", [7, 12, 22, 24])
 def test_tile_widths(tile, M):
-    """S2L tiles of 2 and 8 target boxes (the default is 4), on shapes with
-    partial rows (7, 22) and exact rows (12, 24)."""
+    """Vector-unit S2L tiles of 2 and 8 target boxes, on shapes with partial
+    rows (7, 22) and exact rows (12, 24)."""
     need_gpu()
     r, z, S = inputs.ring_box(900, 3, nrhs=2, seed=400 + M + tile)
     _check(r, z, r, z, S, M, 4, tile=tile)
 
 
 @gpu
-@pytest.mark.parametrize("M,depth,tile", [(0, 4, 0), (1, 4, 0), (2, 4, 0), (3, 4, 0), (5, 4, 0), (7, 4, 0),
-                                          (10, 4, 0), (11, 4, 0), (12, 4, 0), (14, 4, 0), (17, 4, 0), (19, 4, 0),
-                                          (22, 4, 0), (24, 4, 0), (6, 5, 0), (12, 5, 0), (15, 5, 0), (16, 5, 0),
-                                          (20, 5, 0), (23, 5, 0), (24, 5, 0), (24, 5, 8), (9, 6, 0)])
-def test_s2l_matrix_cores(M, depth, tile):
-    """The S2L pass on the FP64 matrix cores: output row tiles of 16 split by
-    column parity, dealt to 1..4 waves of 4..7 tiles (every shape the orders
-    0..24 choose), one column tile of 8 boxes up to level 4 and two (16
-    boxes) from level 5 (tile 8: one everywhere); depth 4 runs levels whose
-    units are split over offset groups (partial sums) and levels written
-    directly."""
+@pytest.mark.parametrize("M,depth", [(0, 4), (1, 4), (2, 4), (3, 4), (5, 4), (7, 4), (10, 4), (11, 4), (12, 4),
+                                     (14, 4), (17, 4), (19, 4), (22, 4), (24, 4), (6, 5), (12, 5), (15, 5), (16, 5),
+                                     (20, 5), (23, 5), (24, 5), (9, 6)])
+def test_s2l_matrix_cores(M, depth):
+    """The S2L pass on the FP64 matrix cores (the default): output row tiles
+    of 16 split by column parity, dealt to row groups of 4..7 tiles (every
+    shape the orders 0..24 choose), one column tile of 8 boxes up to level 4
+    and two (16 boxes) from level 5; depth 4 runs levels whose units are
+    split over offset groups (partial sums) and levels written directly."""
     need_gpu()
     n = {4: 900, 5: 2500, 6: 6000}[depth]
     r, z, S = inputs.ring_box(n, 3, nrhs=2, seed=500 + M + depth)
-    _check(r, z, r, z, S, M, depth, tile=tile, mfma=True)
+    _check(r, z, r, z, S, M, depth)
 
 
 @gpu
