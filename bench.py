@@ -477,8 +477,7 @@ def main():
     secondary = None
     if not args.no_secondary and args.order != CONFIG_ORDER:
         d2, tb2 = autotune_depth(torch, axf, coords, S, nm, CONFIG_ORDER, [4, 5, 6, 7], (0, 2, 4, 8))
-        p2, phi2, ts2, te2, _ = measure(torch, axf, coords, S, nm, CONFIG_ORDER, d2,
-                                        max(3, args.steps // 2), 1, tb2)
+        p2, phi2, ts2, te2, _ = measure(torch, axf, coords, S, nm, CONFIG_ORDER, d2, args.steps, args.warmup, tb2)
         phi2_s = phi2[..., sample].cpu().numpy()
         refs = ref_cpu if eps_oracle is not None else ref_gpu_s
         e2 = (np.abs(phi2_s - refs).max(axis=-1) / np.abs(refs).max(axis=-1)).max()
@@ -493,8 +492,7 @@ def main():
     d_rule = rule_plan.info()["depth"]
     rule_plan.close()
     if d_rule != depth and not args.no_leaf_rule:
-        pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, max(3, args.steps // 2), 1,
-                                        tile)
+        pr, phir, tsr, ter, _ = measure(torch, axf, coords, S, nm, args.order, d_rule, args.steps, args.warmup, tile)
         phir_s = phir[..., sample].cpu().numpy()
         refs = ref_cpu if eps_oracle is not None else ref_gpu_s
         er = (np.abs(phir_s - refs).max(axis=-1) / np.abs(refs).max(axis=-1)).max()
