@@ -598,7 +598,9 @@ __device__ __forceinline__ void s2l_mfma_body(int M, int nmodes, int nrhs, int l
         const int sl = b < nbx ? tslots[tl.z + b] : -1;
         const int bid = sl >= 0 ? tbox[sl] : 0;
         const int zb = bid - (bid / nb) * nb;
-        const int dr0 = -2 - (station & 1), dz0 = -2 - tl.y;
+        // the box's own z parity (a tile may hold both): which of the two
+        // offsets of a unit exist differs, the list of units does not
+        const int dr0 = -2 - (station & 1), dz0 = -2 - (zb & 1);
         int oc = 0, nu = 0;
         for (int dr = dr0; dr < dr0 + 6; ++dr) {
             const int jr = station + dr;
@@ -1477,9 +1479,9 @@ void launch_s2l_mfma(Plan &pl, const Side &src, const Side &tgt, int l, hipStrea
     double2 *part = G > 1 ? pl.s2l_part : nullptr;
     int tpw = 0, waves = 0;
     s2l_mfma_shape(pl.M, tpw, waves);
-    // two column tiles (16 boxes) where a station's column parity holds
-    // more than 8 boxes, else one
-    const bool two = (1 << (l - 1)) > kS2lMfmaBoxes && pl.tb > kS2lMfmaBoxes;
+    // two column tiles (16 boxes) where a station column holds more than 8
+    // boxes, else one
+    const bool two = (1 << l) > kS2lMfmaBoxes && pl.tb > kS2lMfmaBoxes;
 #define AXF_S2L_MFMA(T, NB)                                                                                      \
     k_s2l_mfma<T, NB><<<tgt.ntiles[l] * pl.C * G * waves, 64, 0, st>>>(                                          \
         pl.M, pl.nmodes, pl.nrhs, l, pl.TS, tgt.tiles[l], tgt.tile_slots[l], tgt.box[l], src.slot[l],          \

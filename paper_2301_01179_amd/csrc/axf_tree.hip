@@ -780,15 +780,17 @@ void build_tiles(Plan &pl, hipStream_t st)
             const int nb = 1 << l;
             auto &tv = tiles[si * NL + l];
             auto &sv = slots[si * NL + l];
-            // boxes are station-major in slot order; split each station by parity
+            // boxes are station-major in slot order; the vector S2L splits each
+            // station by z parity (one offset set per tile), the matrix-core
+            // S2L takes a station's boxes in order (each box its own parity)
             int k = 0;
             while (k < n) {
                 int station = bx[k] / nb, e = k;
                 while (e < n && bx[e] / nb == station) ++e;
-                for (int par = 0; par < 2; ++par) {
+                for (int par = 0; par < (pl.mfma ? 1 : 2); ++par) {
                     int first = (int)sv.size();
                     for (int j = k; j < e; ++j)
-                        if (((bx[j] - station * nb) & 1) == par) sv.push_back(j);
+                        if (pl.mfma || ((bx[j] - station * nb) & 1) == par) sv.push_back(j);
                     for (int f = first; f < (int)sv.size(); f += TB)
                         tv.push_back(make_int4(station, par, f, std::min(TB, (int)sv.size() - f)));
                 }
