@@ -29,10 +29,16 @@
  *   R3. M2M / L2L displacement: delta = child centre - parent centre, with
  *       +delta powers (the paper's "-Delta" with Delta = parent - child).
  *   R4. Upward pass ends at level 2 (Algorithm 1), S2L runs on levels 2..d.
- *   R5. Domain: tight bounding square of all source and field points,
+ *   R5. Domain: bounding square of all source and field points,
  *       [r_lo, r_lo+L] x [z_lo, z_lo+L], L = max(r extent, z extent)
- *       (1 if both are zero); box index floor(((r-r_lo)*(1/L))*2^l),
- *       clamped to 2^l - 1.
+ *       (1 if both are zero), z_lo = smallest z.  r_lo = 0 (the paper's
+ *       domain 0 <= r <= r_max) when L reaches the largest radius.  Else,
+ *       if k = floor(r_min / (L/4)) is 1, 2 or 3: L' = the smallest double
+ *       >= max(L, r_max / (1 + k/4)) with k (L'/4) + L' >= r_max, and if
+ *       k (L'/4) <= r_min the square is [k L'/4, k L'/4 + L'] of side L'
+ *       (the levels' stations then sit at whole box units from the axis
+ *       grid).  Else r_lo = smallest radius.  Box index
+ *       floor(((r-r_lo)*(1/L))*2^l), clamped to 2^l - 1.
  *   R6. Moments i+j <= M, locals k+l <= M, derivative tables to total order
  *       2M: the S2L sum of eq. analysis:s2l runs over all i+j <= M.
  *   R7. The starting formulas of App. A (eq. gfunc:derivatives:x and its r,
@@ -630,12 +636,32 @@ static ora_square ora_bounding_square(int64_t ns, const double *rs, const double
     }
     ora_square sq;
     double ext = fmax(rmax - rmin, zmax - zmin);
-    /* side = the larger extent; in r the square starts on the axis (the
-       paper's domain 0 <= r <= r_max) whenever that side still reaches r_max,
-       else at the smallest radius */
-    sq.rlo = rmax <= ext ? 0.0 : rmin;
-    sq.zlo = zmin;
+    /* R5: side = the larger extent; in r on the axis when that side reaches
+       the largest radius, else on k/4 of a (slightly grown) side when the
+       smallest radius is between L/4 and L, else at the smallest radius */
     sq.L = ext > 0.0 ? ext : 1.0;
+    sq.zlo = zmin;
+    sq.rlo = rmin;
+    if (rmax <= sq.L) {
+        sq.rlo = 0.0;
+    } else {
+        double k = floor(rmin / (sq.L * 0.25));
+        if (k >= 1.0 && k <= 3.0) {
+            double f = 1.0 + k * 0.25;
+            double Ls = fmax(sq.L, rmax / f);
+            for (;;) {
+                double r0 = k * (Ls * 0.25);
+                double top = r0 + Ls;
+                if (top >= rmax) break;
+                Ls = nextafter(Ls, INFINITY);
+            }
+            double r0 = k * (Ls * 0.25);
+            if (r0 <= rmin) {
+                sq.L = Ls;
+                sq.rlo = r0;
+            }
+        }
+    }
     sq.invL = 1.0 / sq.L;
     return sq;
 }

@@ -213,19 +213,51 @@ void plan_build(Plan &pl, const axf_params &p, int64_t ns, const double *rs, con
     hipStream_t side = table_stream(pl.device);
     auto start_tables = [&]() {
         const int d = pl.d;
-        // with the square on the axis the stations of every level sit at the
-        // same box-unit radii (s + 1/2), so a level's tables are the finest
-        // level's first stations times 2^(l-d): only those are stored
-        const bool shared = pl.rlo == 0.0;
         // a level's tables cover the radial stations up to that of the
         // largest radius: an S2L operator uses the table of the inner of two
-        // occupied stations, so stations beyond it are never read
+        // occupied stations, so stations beyond it are never read.  With the
+        // square's origin koff L/4 from the axis (koff >= 0), station s of
+        // level l sits at koff 2^(l-2) + s + 1/2 box units, the radius of
+        // station koff 2^(l-2) + s of the finest level's axis grid, so its
+        // tables are that station's times 2^(l-d) (eq. gfunc:scaled): the
+        // levels' station ranges on that grid are merged into runs and only
+        // the runs are stored.  Otherwise every level has its own tables.
         size_t ngeom = 0;
-        for (int l = 2; l <= d; ++l) {
-            pl.tab_smax[l] = box_index(pl.rmax, pl.rlo, pl.invL, shared ? d : l);
-            pl.tab_base[l] = ngeom;
-            if (!shared || l == d) ngeom += (size_t)12 * (pl.tab_smax[l] + 1);
+        pl.tab_runs.clear();
+        if (pl.koff >= 0) {
+            std::vector<std::pair<int, int>> iv;
+            for (int l = 2; l <= d; ++l) {
+                const int v0 = pl.koff << (l - 2);
+                iv.push_back({v0, v0 + box_index(pl.rmax, pl.rlo, pl.invL, l)});
+            }
+            std::sort(iv.begin(), iv.end());
+            for (auto &x : iv) {
+                if (!pl.tab_runs.empty() && x.first <= pl.tab_runs.back().second + 1)
+                    pl.tab_runs.back().second = std::max(pl.tab_runs.back().second, x.second);
+                else
+                    pl.tab_runs.push_back(x);
+            }
+            for (int l = 2; l <= d; ++l) {
+                const int v0 = pl.koff << (l - 2);
+                size_t before = 0;
+                for (auto &run : pl.tab_runs) {
+                    if (v0 >= run.first && v0 <= run.second) {
+                        pl.tab_base[l] = (size_t)12 * (before + (size_t)(v0 - run.first));
+                        pl.tab_smax[l] = std::min((1 << l) - 1, run.second - v0);
+                        break;
+                    }
+                    before += (size_t)(run.second - run.first + 1);
+                }
+            }
+            for (auto &run : pl.tab_runs) ngeom += (size_t)12 * (run.second - run.first + 1);
+        } else {
+            for (int l = 2; l <= d; ++l) {
+                pl.tab_smax[l] = box_index(pl.rmax, pl.rlo, pl.invL, l);
+                pl.tab_base[l] = ngeom;
+                ngeom += (size_t)12 * (pl.tab_smax[l] + 1);
+            }
         }
+        const bool shared = pl.koff >= 0;
         Sizer tz;
         tz.add<double>(ngeom * (size_t)pl.nmodes * pl.TS + kTablePad);
         tz.add<double>(table_scratch_doubles(ngeom, pl.M, pl.nmodes));

@@ -68,11 +68,11 @@ Square plan_square(const std::vector<double> &rs, const std::vector<double> &zs,
             zmin = std::min(zmin, x);
             zmax = std::max(zmax, x);
         }
-    const double ext = std::max(rmax - rmin, zmax - zmin);
     Square q;
-    q.rlo = rmax <= ext ? 0.0 : rmin;
-    q.zlo = zmin;
-    q.invL = 1.0 / (ext > 0.0 ? ext : 1.0);
+    double L = 1.0;
+    int koff = 0;
+    square_rule(rmin, rmax, zmin, zmax, q.rlo, q.zlo, L, koff);
+    q.invL = 1.0 / L;
     return q;
 }
 

@@ -7,6 +7,9 @@
 #include <string>
 #include <functional>
 #include <vector>
+#include <algorithm>
+#include <cmath>
+#include <utility>
 
 #include "axf.h"
 
@@ -115,6 +118,49 @@ inline int s2l_slots(int M, int lb)
 }
 inline int s2l_lb(int M) { return s2l_slots(M, 1) <= 256 ? 1 : 2; }   // 2 fits M <= 24
 inline int s2l_waves(int M) { return (s2l_slots(M, s2l_lb(M)) + 63) / 64; }
+// The bounding square (reading R5): side L = the larger extent (1 if both
+// are zero), from the smallest z.  In r it starts on the axis when that side
+// reaches the largest radius (koff = 0).  Else, when the smallest radius
+// lies between L/4 and L (k = floor(4 r_min / L) in 1..3), on the multiple k
+// of L'/4 with the smallest L' >= L for which k L'/4 + L' reaches the
+// largest radius (L' = r_max / (1 + k/4), raised ulp by ulp until it does),
+// provided k L'/4 is still not above the smallest radius: then the stations
+// of every level sit at whole box units k 2^(l-2) from the axis grid and the
+// levels share tables (koff = k).  Else at the smallest radius (koff = -1).
+// Each operation is rounded on its own (no contraction): the oracle
+// evaluates the same sequence.
+inline void square_rule(double rmin, double rmax, double zmin, double zmax, double &rlo, double &zlo, double &L,
+                        int &koff)
+{
+#pragma clang fp contract(off)
+    const double ext = std::max(rmax - rmin, zmax - zmin);
+    L = ext > 0.0 ? ext : 1.0;
+    zlo = zmin;
+    rlo = rmin;
+    koff = -1;
+    if (rmax <= L) {
+        rlo = 0.0;
+        koff = 0;
+        return;
+    }
+    const double k = std::floor(rmin / (L * 0.25));
+    if (k < 1.0 || k > 3.0) return;
+    const double f = 1.0 + k * 0.25;
+    double Ls = std::max(L, rmax / f);
+    for (;;) {
+        const double r0 = k * (Ls * 0.25);
+        const double top = r0 + Ls;
+        if (top >= rmax) break;
+        Ls = std::nextafter(Ls, INFINITY);
+    }
+    const double r0 = k * (Ls * 0.25);
+    if (r0 <= rmin) {
+        L = Ls;
+        rlo = r0;
+        koff = (int)k;
+    }
+}
+
 // Tile widths the vector-unit S2L kernels are compiled for (boxes per
 // tile), from params.flags (AXF_TILE_SHIFT; 0 there selects the matrix-core
 // kernel); kDefaultTile is the batch kernels' width when none is chosen.
@@ -200,6 +246,10 @@ struct Plan {
     double rmax = 0;                     // largest ring radius of both sets
     int tab_smax[AXF_MAX_DEPTH + 1] = {};   // last radial station with tables, per level
     size_t tab_base[AXF_MAX_DEPTH + 1] = {};   // first geometry of each level in the table storage
+    int koff = -1;                          // square origin in units of L/4 (>= 0: levels share tables)
+    // shared tables: runs [first, last] of finest-level stations of the axis
+    // grid (station v at v + 1/2 box units), stored one after the other
+    std::vector<std::pair<int, int>> tab_runs;
     double chistar = 1e300;
     Side src, fld;
     Level lev[AXF_MAX_DEPTH + 1];

@@ -517,29 +517,35 @@ __global__ __launch_bounds__(kLapThreads) void k_tab_laplace(int M, int nmodes, 
 void build_tables(Plan &pl, hipStream_t st)
 {
     const int M = pl.M, K = 2 * M, nm = pl.nmodes;
-    // geometry list: level, station, separation (only the finest level when
-    // the levels share its tables: square on the axis), for the stations
-    // 0..tab_smax[l] of each level, stored from geometry tab_base[l] on.
+    // geometry list: station, separation; the finest level's stations of the
+    // axis grid in the plan's runs when the levels share tables, else the
+    // stations 0..tab_smax[l] of each level from geometry tab_base[l] on.
     // The plan keeps the list until the copy has run.
     std::vector<GeomDesc> geoms;
-    const bool shared = pl.rlo == 0.0;
-    for (int l = shared ? pl.d : 2; l <= pl.d; ++l) {
-        int nb = 1 << l;
-        double h = pl.L / nb;
-        const size_t base = pl.tab_base[l];
-        for (int s = 0; s <= pl.tab_smax[l]; ++s)
-            for (int gs = 0; gs < 12; ++gs) {
-                int dr = gs < 4 ? gs / 2 : 2 + (gs - 4) / 4;
-                int dz = gs < 4 ? 2 + gs % 2 : (gs - 4) % 4;
-                double rin = pl.rlo / h + s + 0.5;
-                GeomDesc g;
-                g.rin = rin;
-                g.rout = rin + dr;
-                g.x = dz;
-                g.invh = 1.0 / h;
-                g.slot = (double)(base + (size_t)s * 12 + gs);
-                geoms.push_back(g);
-            }
+    auto add = [&](double rin, double h, size_t slot0) {
+        for (int gs = 0; gs < 12; ++gs) {
+            int dr = gs < 4 ? gs / 2 : 2 + (gs - 4) / 4;
+            int dz = gs < 4 ? 2 + gs % 2 : (gs - 4) % 4;
+            GeomDesc g;
+            g.rin = rin;
+            g.rout = rin + dr;
+            g.x = dz;
+            g.invh = 1.0 / h;
+            g.slot = (double)(slot0 + gs);
+            geoms.push_back(g);
+        }
+    };
+    if (pl.koff >= 0) {
+        // shared: the runs of finest-level stations of the axis grid
+        const double h = pl.L / (1 << pl.d);
+        size_t at = 0;
+        for (auto &run : pl.tab_runs)
+            for (int v = run.first; v <= run.second; ++v, ++at) add(v + 0.5, h, 12 * at);
+    } else {
+        for (int l = 2; l <= pl.d; ++l) {
+            const double h = pl.L / (1 << l);
+            for (int s = 0; s <= pl.tab_smax[l]; ++s) add(pl.rlo / h + s + 0.5, h, pl.tab_base[l] + (size_t)s * 12);
+        }
     }
     const int ng = (int)geoms.size();
     const size_t TS = (size_t)(M + 1) * (M + 1) * (M + 1);

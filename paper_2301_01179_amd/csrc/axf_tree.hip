@@ -605,15 +605,8 @@ void build_tree(Plan &pl, const double *rs, const double *zs, const double *rf, 
     std::memcpy(box, pin_box, sizeof(box));
     AXF_REQUIRE(box[4] == 0.0, AXF_ERR_INVALID_GEOMETRY,
                 "a coordinate is not finite or a ring radius is <= 0");
-    double ext = std::max(box[1] - box[0], box[3] - box[2]);
-    // side = the larger extent; in r the square starts on the axis (the
-    // paper's domain 0 <= r <= r_max) whenever that side still reaches r_max
-    // (then every level's stations sit at the same box-unit radii and the
-    // levels share one set of tables), else at the smallest radius
-    pl.rlo = box[1] <= ext ? 0.0 : box[0];
+    square_rule(box[0], box[1], box[2], box[3], pl.rlo, pl.zlo, pl.L, pl.koff);
     pl.rmax = box[1];
-    pl.zlo = box[2];
-    pl.L = ext > 0.0 ? ext : 1.0;
     pl.invL = 1.0 / pl.L;
 
     // ---- depth
