@@ -266,7 +266,12 @@ std::pair<int, int> autotune_model(const axf_problem &pb, int nmodes, const Rate
         for (int t = 0; t < 3; ++t) {
             const Rates &r = rates[t];
             if (r.s2l_unit <= 0) continue;
-            const double tm = w.near * pb.nrhs * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
+            // near-field cost in units of one right-hand side: with G^(n)
+            // shared by the right-hand sides (near_class > 0) each further
+            // one adds about a quarter (measured: 1, 2, 4, 8 right-hand
+            // sides of a 100,000-ring box in 1.3, 1.4, 2.0, 4.3 ms)
+            const double nq = near_class(pb.nrhs, mode_bucket(nmodes)) ? 1.0 + 0.25 * (pb.nrhs - 1) : pb.nrhs;
+            const double tm = w.near * nq * r.near_pair + w.units * C * r.s2l_unit + w.boxes * C * r.box +
                               (double)(pb.ns + pb.nf) * C * r.point;
             model[d][t] = tm;
             if (tm < best_t) {
@@ -286,7 +291,7 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
 {
     const int nprob = (int)plans.size();
     std::vector<ProbDev> pd(nprob);
-    std::vector<int2> qg, qp, ql;
+    std::vector<int2> qg, qp, ql, qlc[4];
     std::vector<std::vector<int2>> qm(AXF_MAX_DEPTH + 1), qlt(AXF_MAX_DEPTH + 1), qs(3 * (AXF_MAX_DEPTH + 1));
     int maxd = 2;
     for (int i = 0; i < nprob; ++i) {
@@ -303,13 +308,18 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
             for (int k = 0; k < pl.fld.ntiles[l] * pl.C; ++k)
                 qs[3 * l + tile_index(pl.tb)].push_back(make_int2(i, k));
         }
-        for (int k = 0; k < pl.fld.nchunks; ++k) ql.push_back(make_int2(i, k));
+        const int cls = near_class(pl.nrhs, pl.nmb);
+        for (int k = 0; k < pl.fld.nchunks; ++k) {
+            ql.push_back(make_int2(i, k));
+            qlc[cls].push_back(make_int2(i, k));
+        }
     }
     Sizer sz;
     sz.add<ProbDev>(nprob);
     sz.add<int2>(qg.size() + 1);
     sz.add<int2>(qp.size() + 1);
     sz.add<int2>(ql.size() + 1);
+    for (int c = 0; c < 4; ++c) sz.add<int2>(qlc[c].size() + 1);
     for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
         sz.add<int2>(qm[l].size() + 1);
         sz.add<int2>(qlt[l].size() + 1);
@@ -327,6 +337,7 @@ void build_queues(const std::vector<Plan *> &plans, const std::vector<const doub
     up(qg, q.gather, q.ngather);
     up(qp, q.p2m, q.np2m);
     up(ql, q.leaf, q.nleaf);
+    for (int c = 0; c < 4; ++c) up(qlc[c], q.leafq[c], q.nleafq[c]);
     for (int l = 0; l <= AXF_MAX_DEPTH; ++l) {
         up(qm[l], q.m2m[l], q.nm2m[l]);
         up(qlt[l], q.l2l[l], q.nl2l[l]);

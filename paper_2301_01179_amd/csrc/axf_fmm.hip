@@ -966,17 +966,16 @@ __device__ __forceinline__ void fwd_step(int n, double dchi, double &g, double &
     g -= dg;
 }
 
-// Adds S_s^(n) G^(n)(r, r1, x) for n < nmodes of one pair per lane.  All
-// lanes of the wave call it together (the backward recursion runs a
-// wave-wide number of steps).  `use` = false lanes contribute nothing.
-// The wave takes one of three mode streams: all pairs forward (recursion
-// streams into the accumulators), all backward (normalised Miller values),
-// or mixed (both, selected per lane).  Ss points at the source's strengths
-// of modes 0..NMB-1 for this right-hand side (zero beyond nmodes).
-template <int NMB, int MODE>
-__device__ __forceinline__ void pair_accum(double r, double r1, double x, double inv_r, double inv_r1, bool use,
-                                           double chistar, int nmodes, const double2 *Ss,
-                                           Acc<NMB, MODE> &A, double *__restrict__ lg)
+// The G^(n)(r, r1, x), n < NMB, of one pair per lane, handed to sink(n,
+// G^(n), gprev, pd) in increasing n (gprev, pd: the previous value and the
+// pair's derivative data, for the gradient accumulators).  All lanes of the
+// wave call it together (the backward recursion runs a wave-wide number of
+// steps).  `use` = false lanes get zeros.  The wave takes one of three mode
+// streams: all pairs forward (the recursion streams into the sink), all
+// backward (normalised Miller values), or mixed (both, selected per lane).
+template <int NMB, int MODE, class Sink>
+__device__ __forceinline__ void pair_visit(double r, double r1, double x, double inv_r, double inv_r1, bool use,
+                                           double chistar, int nmodes, double *__restrict__ lg, Sink &&sink)
 {
     const int lane = threadIdx.x & 63;
     const double dr = r - r1, sr = r + r1;
@@ -1073,9 +1072,7 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
     if (MODE == 0 && NMB > 2 && allback) {
         double gprev = bv.get(1);               // G^(-1) = G^(1)
 #pragma unroll
-        for (int n = 0; n < NMB; ++n) {
-            accum_mode<NMB, MODE>(A, n, bv.get(n), gprev, Ss[n], pd);
-        }
+        for (int n = 0; n < NMB; ++n) sink(n, bv.get(n), gprev, pd);
         return;
     }
     // forward recursion (in differences, fwd_step) streamed over the modes
@@ -1093,9 +1090,23 @@ __device__ __forceinline__ void pair_accum(double r, double r1, double x, double
         if constexpr (NMB > 2) {
             if (anyback) g = back ? bv.get(n) : g;
         }
-        accum_mode<NMB, MODE>(A, n, g, gprev, Ss[n], pd);
+        sink(n, g, gprev, pd);
         if (n + 1 < NMB) fwd_step(n, dchi, gcur, dg);
     }
+}
+
+// Adds S_s^(n) G^(n)(r, r1, x) for n < nmodes of one pair per lane (Ss: the
+// source's strengths of modes 0..NMB-1 for this right-hand side, zero
+// beyond nmodes).
+template <int NMB, int MODE>
+__device__ __forceinline__ void pair_accum(double r, double r1, double x, double inv_r, double inv_r1, bool use,
+                                           double chistar, int nmodes, const double2 *Ss,
+                                           Acc<NMB, MODE> &A, double *__restrict__ lg)
+{
+    pair_visit<NMB, MODE>(r, r1, x, inv_r, inv_r1, use, chistar, nmodes, lg,
+                          [&](int n, double g, double &gprev, const PairDeriv &pd) {
+                              accum_mode<NMB, MODE>(A, n, g, gprev, Ss[n], pd);
+                          });
 }
 
 // Launch shape of the pair kernels per mode bucket: waves per block (each
@@ -1328,6 +1339,127 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_leaf(
                                dphr, dphz, dpha, Sdot, gr, gz, ntot, Cs, blockIdx.x);
 }
 
+// ------------------------------------------- near field, shared G^(n)
+// Near field of a potential evaluation with several right-hand sides and at
+// most 24 modes: G^(n) of a (target, source) pair is computed once for every
+// right-hand side.  A wave serves 64 / QP targets with QP lanes each (QP =
+// nrhs rounded up to 2, 4 or 8; lane q of a target accumulates right-hand
+// side q).  In each step the QP lanes of a target take QP consecutive
+// sources, write their G^(n) to the wave's LDS rows, and each lane then adds
+// G^(n) S_q^(n) of all QP sources (the sources in order, as the one-source
+// kernel does).  A block has QP waves, the <= 64 targets of one chunk; every
+// wave walks all sources of the 3 x 3 neighbour leaves, staged in LDS in
+// tiles of 32 (QP = 2, 4) or 16 (QP = 8) sources.  The result goes to phi;
+// the local expansions are added by k_l2p.
+template <int NMB, int QP>
+struct NearQShape {
+    static constexpr int ST = QP == 2 ? 32 : 128 / QP;           // sources per staged tile
+    static constexpr size_t kLdsBytes = sizeof(double) * ((size_t)QP * NMB * 64 + 3 * ST) +
+                                        sizeof(double2) * (size_t)ST * NMB * QP;
+};
+
+template <int NMB, int QP>
+__device__ __forceinline__ void leaf_q_body(int nmodes, int nrhs, int depth, double chistar,
+                                            const int4 *__restrict__ chunks, SideView tv, SideView sv,
+                                            const double *__restrict__ sinv, const double2 *__restrict__ Sg,
+                                            double2 *__restrict__ phi, int64_t ntot, int Cs, int item)
+{
+    constexpr int ST = NearQShape<NMB, QP>::ST, TPW = 64 / QP;
+    extern __shared__ double lds[];
+    double *gl_all = lds;                                        // [QP waves][NMB][64]
+    double *st_r = lds + (size_t)QP * NMB * 64;
+    double *st_z = st_r + ST, *st_i = st_z + ST;
+    double2 *st_S = reinterpret_cast<double2 *>(st_i + ST);     // [ST][NMB][QP]
+    const int4 ch = chunks[item];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int tl = lane / QP, q = lane - (lane / QP) * QP;
+    double *gl = gl_all + (size_t)w * NMB * 64;
+    const int tix = w * TPW + tl;                               // target of the chunk
+    const bool active = tix < ch.z;
+    const int t = ch.y + (active ? tix : 0);
+    const int nb = 1 << depth;
+    const int ir = ch.w / nb, iz = ch.w - (ch.w / nb) * nb;
+    const double r = tv.r[t], z = tv.z[t];
+    const double inv_r = fast_rcp(r);
+    Acc<NMB, 0> A;
+    A.zero();
+    int rb[9], re[9], nr = 0, total = 0;
+    for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
+        for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) {
+            const uint32_t m = morton((uint32_t)jr, (uint32_t)jz);
+            rb[nr] = sv.off[m];
+            re[nr] = sv.off[m + 1];
+            total += re[nr] - rb[nr];
+            ++nr;
+        }
+    for (int tile = 0; tile < total; tile += ST) {
+        __syncthreads();
+        const int cnt = min(ST, total - tile);
+        for (int e = threadIdx.x; e < cnt * NMB * QP; e += 64 * QP) {
+            const int k = e / (NMB * QP), rem = e - k * (NMB * QP);
+            const int n = rem / QP, qq = rem - (rem / QP) * QP;
+            int li = tile + k, rr = 0;
+            while (li >= re[rr] - rb[rr]) {
+                li -= re[rr] - rb[rr];
+                ++rr;
+            }
+            const int src = rb[rr] + li;
+            st_S[e] = qq < nrhs ? Sg[(int64_t)src * Cs + n * nrhs + qq] : make_double2(0.0, 0.0);
+            if (rem == 0) {
+                st_r[k] = sv.r[src];
+                st_z[k] = sv.z[src];
+                st_i[k] = sinv[src];
+            }
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < cnt; k0 += QP) {
+            // this lane's pair: its target with source k0 + q
+            const int k = min(k0 + q, cnt - 1);
+            const double r1 = st_r[k], x = z - st_z[k];
+            const bool use = active && k0 + q < cnt && !(r == r1 && x == 0.0);
+            pair_visit<NMB, 0>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, nullptr,
+                               [&](int n, double g, double &, const PairDeriv &) { gl[n * 64 + lane] = g; });
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // G^(n) of the target's QP pairs (lanes tl QP .. tl QP + QP - 1)
+            // against this lane's right-hand side, sources in order
+#pragma unroll
+            for (int qs = 0; qs < QP; ++qs) {
+                if (k0 + qs >= cnt) break;                           // uniform
+                const double *gq = gl + tl * QP + qs;
+                const double2 *Sq = st_S + ((size_t)(k0 + qs) * NMB) * QP + q;
+#pragma unroll
+                for (int n = 0; n < NMB; ++n) {
+                    const double g = gq[n * 64];
+                    const double2 v = Sq[n * QP];
+                    A.ar[n] = fma(g, v.x, A.ar[n]);
+                    A.ai[n] = fma(g, v.y, A.ai[n]);
+                }
+            }
+            // every lane has read the rows before the next step rewrites them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if (active && q < nrhs) {
+        const int orig = tv.perm[t];
+#pragma unroll
+        for (int n = 0; n < NMB; ++n)
+            if (n < nmodes) phi[((int64_t)q * nmodes + n) * ntot + orig] = make_double2(A.ar[n], A.ai[n]);
+    }
+}
+
+template <int NMB, int QP>
+__global__ __launch_bounds__(64 * QP) void k_leaf_q(int nmodes, int nrhs, int depth, double chistar,
+                                                    const int4 *__restrict__ chunks, SideView tv, SideView sv,
+                                                    const double *__restrict__ sinv, const double2 *__restrict__ Sg,
+                                                    double2 *__restrict__ phi, int64_t ntot, int Cs)
+{
+    leaf_q_body<NMB, QP>(nmodes, nrhs, depth, chistar, chunks, tv, sv, sinv, Sg, phi, ntot, Cs, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ L2P
 // Local expansions at the field points (eq. analysis:local), added to the
 // near field already in phi: one block per (chunk of <= 64 targets, group of
@@ -1558,6 +1690,29 @@ void launch_leaf(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out,
     else launch_leaf_mode<NMB, 2>(pl, src, tgt, out, st);
 }
 
+// Near field with G^(n) shared by the right-hand sides (potential, nrhs >= 2,
+// NMB <= kNearQMaxModes); QP = nrhs rounded up to 2, 4 or 8.
+template <int NMB, int QP>
+void launch_leaf_q_t(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
+{
+    constexpr size_t shm = NearQShape<NMB, QP>::kLdsBytes;
+    static bool attr[64] = {};
+    allow_lds(k_leaf_q<NMB, QP>, shm, pl.device, attr);
+    k_leaf_q<NMB, QP><<<tgt.nchunks, 64 * QP, shm, st>>>(pl.nmodes, pl.nrhs, pl.d, pl.chistar, tgt.chunks,
+                                                         view_of(tgt), view_of(src), src.rinv, pl.Sg,
+                                                         (double2 *)out.phi, tgt.n, NMB * pl.nrhs);
+}
+
+template <int NMB>
+void launch_leaf_q(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
+{
+    if constexpr (NMB <= kNearQMaxModes) {
+        if (pl.nrhs <= 2) launch_leaf_q_t<NMB, 2>(pl, src, tgt, out, st);
+        else if (pl.nrhs <= 4) launch_leaf_q_t<NMB, 4>(pl, src, tgt, out, st);
+        else launch_leaf_q_t<NMB, 8>(pl, src, tgt, out, st);
+    }
+}
+
 template <int NMB>
 void launch_direct(Plan &pl, const Side &src, const Side &tgt, const EvalOut &out, hipStream_t st)
 {
@@ -1674,6 +1829,21 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void kb_leaf(const ProbDe
     }
 }
 
+// Near field with G^(n) shared by QP right-hand-side lanes, over a queue of
+// (problem, chunk) items of problems with the same lane count.
+template <int NMB, int QP>
+__global__ __launch_bounds__(64 * QP) void kb_leaf_q(const ProbDev *__restrict__ P, const int2 *__restrict__ q,
+                                                     int n, int nmodes, double chistar)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int2 it = q[i];
+        ConstProbDev &pd = ((ConstProbDev *)P)[it.x];
+        __syncthreads();
+        leaf_q_body<NMB, QP>(nmodes, pd.nrhs, pd.d, chistar, pd.chunks, view_of(pd.tv), view_of(pd.sv), pd.srinv,
+                             pd.Sg, pd.phi, pd.nf, pd.Cs, it.y);
+    }
+}
+
 // Local expansions of every chunk of the leaf queue, all channel groups.
 __global__ __launch_bounds__(64 * kL2PChannels) void kb_l2p(const ProbDev *__restrict__ P,
                                                             const int2 *__restrict__ q, int n, int M, int nmodes)
@@ -1706,17 +1876,39 @@ void launch_s2l_batch(const BatchQueues &bq, int l, hipStream_t st)
                                                                    bq.nmodes, bq.TS, l);
 }
 
-template <int NMB, int PART>
-void launch_leaf_batch(const BatchQueues &bq, hipStream_t st)
+
+template <int NMB, int QP>
+void launch_leafq_batch_t(const BatchQueues &bq, int c, hipStream_t st)
 {
-    constexpr size_t shm = leaf_lds_bytes<NMB, 0>();
+    constexpr size_t shm = NearQShape<NMB, QP>::kLdsBytes;
     static bool attr[64] = {};
     int dev = 0;
     AXF_HIP(hipGetDevice(&dev));
-    allow_lds(kb_leaf<NMB, PART>, shm, dev, attr);
-    int g = std::min(bq.nleaf, kPersistBlocks);
-    kb_leaf<NMB, PART><<<g, 64 * PairShape<NMB>::WPB, shm, st>>>(bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes,
-                                                                   bq.chistar);
+    allow_lds(kb_leaf_q<NMB, QP>, shm, dev, attr);
+    kb_leaf_q<NMB, QP><<<std::min(bq.nleafq[c], kPersistBlocks), 64 * QP, shm, st>>>(bq.probs, bq.leafq[c],
+                                                                                    bq.nleafq[c], bq.nmodes,
+                                                                                    bq.chistar);
+}
+
+// The near field of every leaf chunk (potential only; the local expansions
+// follow in kb_l2p): each near-field class with its kernel.
+template <int NMB>
+void launch_near_batch(const BatchQueues &bq, hipStream_t st)
+{
+    if (bq.nleafq[0]) {
+        constexpr size_t shm = leaf_lds_bytes<NMB, 0>();
+        static bool attr[64] = {};
+        int dev = 0;
+        AXF_HIP(hipGetDevice(&dev));
+        allow_lds(kb_leaf<NMB, 1>, shm, dev, attr);
+        kb_leaf<NMB, 1><<<std::min(bq.nleafq[0], kPersistBlocks), 64 * PairShape<NMB>::WPB, shm, st>>>(
+            bq.probs, bq.leafq[0], bq.nleafq[0], bq.M, bq.nmodes, bq.chistar);
+    }
+    if constexpr (NMB <= kNearQMaxModes) {
+        if (bq.nleafq[1]) launch_leafq_batch_t<NMB, 2>(bq, 1, st);
+        if (bq.nleafq[2]) launch_leafq_batch_t<NMB, 4>(bq, 2, st);
+        if (bq.nleafq[3]) launch_leafq_batch_t<NMB, 8>(bq, 3, st);
+    }
 }
 
 // ------------------------------------------------------------- census
@@ -1868,6 +2060,9 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
     // the short upward pass so that it does not hold the CUs that pass
     // needs; the local expansions are added once both are done
     const bool split = out.mode == 0 && !out.fused && pl.overlap && tgt.nchunks > 0;
+    // several right-hand sides: the near field computes each pair's G^(n)
+    // once for all of them (then the local expansions are added by k_l2p)
+    const bool multi = out.mode == 0 && !out.fused && near_class(pl.nrhs, pl.nmb) > 0 && tgt.nchunks > 0;
     SideView sv = view_of(src);
     if (src.nocc[d] > 0) {
         PhaseTimer tm(pl, st, AXF_PHASE_P2M);
@@ -1887,8 +2082,11 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
         AXF_HIP(hipStreamWaitEvent(side, pl.ev_fork, 0));
         {
             PhaseTimer tm(pl, side, AXF_PHASE_LEAF);
-#define AXF_NEAR(B) \
-    if (pl.nmb == B) launch_leaf<B>(pl, src, tgt, out, side, 1);
+#define AXF_NEAR(B)                                                   \
+    if (pl.nmb == B) {                                                \
+        if (multi) launch_leaf_q<B>(pl, src, tgt, out, side);         \
+        else launch_leaf<B>(pl, src, tgt, out, side, 1);              \
+    }
             AXF_BUCKETS(AXF_NEAR)
 #undef AXF_NEAR
         }
@@ -1903,8 +2101,15 @@ void run_fmm(Plan &pl, const Side &src, const Side &tgt, const double *S, const 
         }
     }
     (void)pl.nmodes;
-    if (split) {
-        AXF_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
+    if (multi && !split) {
+        PhaseTimer tm(pl, st, AXF_PHASE_LEAF);
+#define AXF_NEARQ(B) \
+    if (pl.nmb == B) launch_leaf_q<B>(pl, src, tgt, out, st);
+        AXF_BUCKETS(AXF_NEARQ)
+#undef AXF_NEARQ
+    }
+    if (split || multi) {
+        if (split) AXF_HIP(hipStreamWaitEvent(st, pl.ev_join, 0));
         PhaseTimer tm(pl, st, AXF_PHASE_L2P);
         const int ngrp = (C + kL2PChannels - 1) / kL2PChannels;
         k_l2p<<<tgt.nchunks * ngrp, 64 * kL2PChannels, sizeof(double2) * kL2PChannels * P, st>>>(
@@ -1961,7 +2166,7 @@ void run_batch(const BatchQueues &bq, hipStream_t st, const BatchSide *side)
         AXF_HIP(hipEventRecord(side->fork, st));
         AXF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
 #define AXF_NEARB(B)                                    \
-    if (bq.nmb == B) launch_leaf_batch<B, 1>(bq, side->stream);
+    if (bq.nmb == B) launch_near_batch<B>(bq, side->stream);
         AXF_BUCKETS(AXF_NEARB)
 #undef AXF_NEARB
         AXF_HIP(hipEventRecord(side->join, side->stream));
@@ -1980,18 +2185,18 @@ void run_batch(const BatchQueues &bq, hipStream_t st, const BatchSide *side)
 #undef AXF_S2L_LAUNCH4
 #undef AXF_S2L_LAUNCH8
     }
-    if (split) {
-        AXF_HIP(hipStreamWaitEvent(st, side->join, 0));
+    if (bq.nleaf) {
+        if (split) {
+            AXF_HIP(hipStreamWaitEvent(st, side->join, 0));
+        } else {
+#define AXF_NEARB(B) \
+    if (bq.nmb == B) launch_near_batch<B>(bq, st);
+            AXF_BUCKETS(AXF_NEARB)
+#undef AXF_NEARB
+        }
         const int P = (bq.M + 1) * (bq.M + 2) / 2;
         kb_l2p<<<std::min(bq.nleaf, kPersistBlocks), 64 * kL2PChannels, sizeof(double2) * kL2PChannels * P, st>>>(
             bq.probs, bq.leaf, bq.nleaf, bq.M, bq.nmodes);
-    } else if (bq.nleaf) {
-#define AXF_LEAFB(B)                          \
-    if (bq.nmb == B) {                        \
-        launch_leaf_batch<B, 0>(bq, st);      \
-    }
-        AXF_BUCKETS(AXF_LEAFB)
-#undef AXF_LEAFB
     }
     AXF_HIP(hipGetLastError());
 }

@@ -161,6 +161,16 @@ inline void square_rule(double rmin, double rmax, double zmin, double zmax, doub
     }
 }
 
+// Near field with G^(n) shared by the right-hand sides: up to this many
+// modes (mode buckets up to 24); the class of a plan: 0 = one source per
+// lane step (nrhs 1, or more modes), 1, 2, 3 = 2, 4, 8 lanes per target.
+constexpr int kNearQMaxModes = 24;
+inline int near_class(int nrhs, int nmb)
+{
+    if (nrhs < 2 || nmb > kNearQMaxModes) return 0;
+    return nrhs <= 2 ? 1 : nrhs <= 4 ? 2 : 3;
+}
+
 // Tile widths the vector-unit S2L kernels are compiled for (boxes per
 // tile), from params.flags (AXF_TILE_SHIFT; 0 there selects the matrix-core
 // kernel); kDefaultTile is the batch kernels' width when none is chosen.
@@ -398,6 +408,10 @@ struct BatchQueues {
     const ProbDev *probs = nullptr;
     int2 *gather = nullptr, *p2m = nullptr, *leaf = nullptr;
     int ngather = 0, np2m = 0, nleaf = 0;
+    // the leaf chunks again by near-field kernel: [0] one source per lane
+    // step, [1..3] G^(n) shared by 2, 4, 8 right-hand-side lanes
+    int2 *leafq[4] = {};
+    int nleafq[4] = {};
     int2 *m2m[AXF_MAX_DEPTH + 1] = {}, *l2l[AXF_MAX_DEPTH + 1] = {};
     int nm2m[AXF_MAX_DEPTH + 1] = {}, nl2l[AXF_MAX_DEPTH + 1] = {};
     // S2L tiles of level l of the problems whose tile width is kTiles[t]

@@ -142,6 +142,26 @@ def test_s2l_matrix_cores(M, depth):
 
 
 @gpu
+@pytest.mark.parametrize("nmodes,nrhs,overlap", [(3, 2, True), (9, 3, True), (17, 4, True), (17, 5, False),
+                                                 (24, 8, True), (12, 7, False), (17, 2, False), (30, 4, True)])
+def test_near_shared_rhs(nmodes, nrhs, overlap):
+    """Potential evaluations with several right-hand sides compute each
+    near-field pair's G^(n) once for all of them (2, 4 or 8 lanes per target,
+    idle lanes for 3, 5, 7; 30 modes keep the one-source kernel), beside the
+    downward pass or after it."""
+    need_gpu()
+    axf = _axf()
+    r, z, S = inputs.ring_box(700, nmodes, nrhs=nrhs, seed=900 + nmodes + nrhs)
+    plan = axf.Plan(r, z, r, z, nmodes, 8, depth=3, nrhs=nrhs, overlap=overlap)
+    phi = to_np(plan.evaluate(torch.from_numpy(S)))
+    ref = O.fmm(r, z, r, z, S, 8, 3)
+    e = rel_err(phi, ref)
+    assert np.all(np.isfinite(phi))
+    assert e.max() < TOL, e.max()
+    plan.close()
+
+
+@gpu
 @pytest.mark.parametrize("nmodes", [11, 20, 40])
 def test_mode_buckets(nmodes):
     """11, 20 and 40 modes run the near-field kernels compiled for 12, 24 and
