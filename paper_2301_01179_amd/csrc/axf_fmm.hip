@@ -1186,7 +1186,8 @@ constexpr size_t leaf_lds_bytes()
 // ------------------------------------------------------------ leaf pass
 // One block (four waves) per chunk of <= 64 targets of one leaf: local
 // expansion (eq. analysis:local) plus the direct sum over the 3x3 neighbour
-// leaves, the sources dealt round-robin to the four waves.
+// leaves, the sources dealt round-robin to the four waves (and to the lane
+// groups of a wave when the chunk has 32 targets or fewer).
 // MODE 0: potential; 1: potential and gradient; 2: potential and the
 // adjoint coordinate contraction.  PART 0: both sums; PART 1 (MODE 0): the
 // near field only, written to phi (it needs no local expansions, so it runs
@@ -1209,8 +1210,17 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
     double *st_z = st_r + ST, *st_i = st_z + ST;
     const int4 ch = chunks[item];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const bool active = lane < ch.z;
-    const int t = ch.y + (active ? lane : 0);
+    // a chunk of T targets takes tp lanes (T rounded up to a power of two)
+    // per group and SG = 64 / tp groups per wave; the groups take different
+    // sources of each staged tile and are summed before the cross-wave
+    // reduction, so that small chunks (the last of a leaf, small leaves)
+    // leave no lanes idle
+    const int T = ch.z;
+    const int tp = T > 32 ? 64 : T > 16 ? 32 : T > 8 ? 16 : T > 4 ? 8 : T > 2 ? 4 : T > 1 ? 2 : 1;
+    const int SG = 64 / tp;
+    const int tl = lane & (tp - 1), sg = lane / tp;
+    const bool active = tl < T;
+    const int t = ch.y + (active ? tl : 0);
     const int nb = 1 << depth;
     const int ir = ch.w / nb, iz = ch.w - (ch.w / nb) * nb;
     const int P = (M + 1) * (M + 2) / 2;
@@ -1225,7 +1235,8 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
     for (int q = 0; q < nrhs; ++q) {
         Acc<NMB, MODE> A;
         A.zero();
-        // local expansion, monomials dealt round-robin over the waves
+        // local expansion, monomials dealt round-robin over the (wave,
+        // group) slots
         const double2 *lc = loc + (int64_t)ch.x * C * P;
         if constexpr (PART != 1) {
             double pr = 1.0, pr1 = 0.0;
@@ -1233,7 +1244,7 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
             for (int kk = 0; kk <= M; ++kk) {
                 double pz = 1.0, pz1 = 0.0;
                 for (int ll = 0; kk + ll <= M; ++ll, ++p) {
-                    if (p % WPB == w) {
+                    if (p % (WPB * SG) == w * SG + sg) {
                         const double wv = pr * pz;
 #pragma unroll
                         for (int n = 0; n < NMB; ++n) {
@@ -1289,14 +1300,34 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
                 }
             }
             __syncthreads();
-            for (int k = w; k < cnt; k += WPB) {
+            // slot w SG + sg of every WPB SG sources (a lane past the tile's
+            // end reads its group's first source and adds nothing)
+            for (int kb = w * SG; kb < cnt; kb += WPB * SG) {
+                const int k = kb + sg < cnt ? kb + sg : kb;
                 const double r1 = st_r[k], x = z - st_z[k];
-                const bool use = active && !(r == r1 && x == 0.0);
+                const bool use = active && kb + sg < cnt && !(r == r1 && x == 0.0);
                 pair_accum<NMB, MODE>(r, r1, x, inv_r, st_i[k], use, chistar, nmodes, st_S + k * NMB, A, lg);
             }
         }
+        if (SG > 1) {
+            // the groups' sums, by a fixed butterfly (the same order every call)
+            auto fold = [&](double &v) {
+                for (int off = tp; off < 64; off <<= 1) v += __shfl_xor(v, off);
+            };
+#pragma unroll
+            for (int n = 0; n < NMB; ++n) {
+                fold(A.ar[n]);
+                fold(A.ai[n]);
+                if constexpr (MODE != 0) {
+                    fold(A.rr_[n]);
+                    fold(A.ri_[n]);
+                    fold(A.zr_[n]);
+                    fold(A.zi_[n]);
+                }
+            }
+        }
         reduce_waves<NMB, MODE, WPB>(A, lds);
-        if (w == 0 && active) {
+        if (w == 0 && active && sg == 0) {
 #pragma unroll
             for (int n = 0; n < NMB; ++n) {
                 if (n < nmodes) {
@@ -1319,7 +1350,7 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
         __syncthreads();
     }
     if constexpr (MODE == 2) {
-        if (w == 0 && active) {
+        if (w == 0 && active && sg == 0) {
             if (gr) gr[orig] = gsr;
             if (gz) gz[orig] = gsz;
         }
