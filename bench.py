@@ -316,7 +316,24 @@ def measure_adjoint(torch, axf, inputs, dev):
                                 "frac": round(total / t_a / 1e12 / PEAK_FP64_VALU_TFLOPS, 4),
                                 "phases": roof_a,
                                 "note": "forward work model (potential part of the leaf only)"}}
+    d_rule = plan.info()["depth"]
+    out["depth_choice"] = "the workload's <= 32 points-per-leaf rule"
     plan.close()
+    # the same workload at the fastest of the depths around the rule's
+    best = None
+    for d in (d_rule - 2, d_rule - 1, d_rule):
+        p = axf.Plan(rt, zt, rt, zt, nm, M, depth=d)
+        phi = p.evaluate(S)
+        g = 2 * (phi - p.evaluate(St))
+        p.adjoint(g, S)
+        tf = _median_time(torch, lambda: p.evaluate(S), 3)
+        ta = _median_time(torch, lambda: p.adjoint(g, S), 3)
+        if best is None or tf + ta < best[1] + best[2]:
+            best = (d, tf, ta)
+        p.close()
+    out["fastest_depth"] = {"depth": best[0], "ms_forward": best[1] * 1e3, "ms_adjoint": best[2] * 1e3,
+                            "adjoint_value": units / best[2],
+                            "choice": "fastest forward + adjoint of depths rule-2 .. rule"}
     return out
 
 
