@@ -105,8 +105,8 @@ struct Side {
 // Shape of the tiled S2L: output slots of one (box, channel) are rows k
 // whose even and odd columns are each split into blocks of LB (columns l0,
 // l0 + 2, ...); LB is the smallest width whose slots fit in four waves, the
-// block has one wave per 64 slots, and a tile holds TB target boxes (4:
-// measured best against 2, 8 and 16 at M = 24).
+// block has one wave per 64 slots, and a tile holds TB = 2, 4 or 8 target
+// boxes (the plan's tile width).
 inline int s2l_slots(int M, int lb)
 {
     int s = 0;
