@@ -1038,9 +1038,12 @@ __device__ __forceinline__ void pair_visit(double r, double r1, double x, double
             }
             // back to G-scaled values with w_(NMB-1) = 1: y_(NMB-1), y_NMB
             double y = zc, yp = c_down.rho[NMB] * zp;
-            // keep the growth of the last NMB-1 steps in range
-            int e = ilogb(y) + (int)ceil((NMB - 1) * log2(lam)) - 16;
-            int emax = ilogb(y) + 1000;
+            // keep the growth of the last NMB-1 steps (at most lam per step)
+            // in range: lam < 2^(ilogb(lam) + 1) bounds it without a
+            // logarithm; a power-of-two scale changes no rounding
+            const int ey = ilogb(y);
+            int e = ey + (NMB - 1) * (ilogb(lam) + 1) - 16;
+            int emax = ey + 1000;
             if (e > emax) e = emax;
             y = ldexp(y, -e);
             yp = ldexp(yp, -e);
