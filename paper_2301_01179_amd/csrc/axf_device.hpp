@@ -36,12 +36,11 @@ struct DownCoef {
 };
 static __constant__ DownCoef c_down = DownCoef();
 
-__device__ __forceinline__ double wave_min(double v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_min_f64(double);
+
+// Minimum over the wave's lanes (the device library's cross-lane reduction:
+// data-parallel lane moves instead of six dependent LDS permutes).
+__device__ __forceinline__ double wave_min(double v) { return __ockl_wfred_min_f64(v); }
 
 // Forward-recursion limit.  Rounding in the forward recursion grows like
 // lambda^(2n), lambda = chi + sqrt(chi^2 - 1) = e^eta, relative to G^(n).
