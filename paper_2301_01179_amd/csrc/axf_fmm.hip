@@ -1186,6 +1186,85 @@ constexpr size_t leaf_lds_bytes()
     return leaf_lds_doubles<NMB, MODE>() * sizeof(double) + (size_t)ST * NMB * 16 + 3 * ST * sizeof(double);
 }
 
+// Strength loads per staging round and thread, by mode bucket: as many as
+// the kernels' registers allow without losing a wave per SIMD.
+template <int NMB>
+constexpr int kStageLoads = NMB == 17 ? 4 : NMB <= 12 ? 2 : 1;
+
+// One tile of sources into LDS for the pair kernels (NT threads): element
+// e < nel of st_S is val(e), and source k < cnt (cnt <= NT) has its r, z and
+// 1/r at st_[rzi][k], source index src_of(k).  Every thread issues its
+// coordinate loads and up to four strength loads before its first LDS write,
+// so a tile waits about one memory latency, not one per element (B loads
+// per round: fewer where the kernel's registers are scarce).
+template <int NT, int B, class SrcOf, class Val>
+__device__ __forceinline__ void stage_tile(int cnt, int nel, SrcOf src_of, Val val, const SideView &sv,
+                                           const double *__restrict__ sinv, double2 *__restrict__ st_S,
+                                           double *__restrict__ st_r, double *__restrict__ st_z,
+                                           double *__restrict__ st_i)
+{
+    const int tid = threadIdx.x;
+    const bool crd = tid < cnt;
+    double cr = 0.0, cz = 0.0, ci = 0.0;
+    if (crd) {
+        const auto sidx = src_of(tid);
+        cr = sv.r[sidx];
+        cz = sv.z[sidx];
+        ci = sinv[sidx];
+    }
+    for (int base = 0; base < nel; base += B * NT) {
+        double2 v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int e = base + b * NT + tid;
+            v[b] = e < nel ? val(e) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int e = base + b * NT + tid;
+            if (e < nel) st_S[e] = v[b];
+        }
+    }
+    if (crd) {
+        st_r[tid] = cr;
+        st_z[tid] = cz;
+        st_i[tid] = ci;
+    }
+}
+
+// The sources of the 3 x 3 neighbour leaves of leaf (ir, iz) as one list,
+// leaf by leaf (r outer, z inner; leaves outside the domain are empty):
+// item li is source li + d_i of the tree order, i the last of the nine
+// leaves whose start cb[i] in the list is <= li; d_i is accumulated from the
+// steps inc[i] = d_i - d_(i-1) (the starts do not decrease), so that no
+// array is indexed at run time and the list stays in registers.
+struct NearList {
+    int cb[9], inc[9], total;
+    __device__ __forceinline__ NearList(const int32_t *__restrict__ off, int ir, int iz, int nb)
+    {
+        total = 0;
+        int dprev = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int jr = ir + i / 3 - 1, jz = iz + i % 3 - 1;
+            const bool in = jr >= 0 && jr < nb && jz >= 0 && jz < nb;
+            const uint32_t m = in ? morton((uint32_t)jr, (uint32_t)jz) : 0u;
+            const int b = in ? off[m] : 0, e = in ? off[m + 1] : 0;
+            cb[i] = total;
+            inc[i] = (b - total) - dprev;
+            dprev = b - total;
+            total += e - b;
+        }
+    }
+    __device__ __forceinline__ int source(int li) const
+    {
+        int d = inc[0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) d += li >= cb[i] ? inc[i] : 0;
+        return li + d;
+    }
+};
+
 // ------------------------------------------------------------ leaf pass
 // One block (four waves) per chunk of <= 64 targets of one leaf: local
 // expansion (eq. analysis:local) plus the direct sum over the 3x3 neighbour
@@ -1275,33 +1354,18 @@ __device__ __forceinline__ void leaf_body(int M, int nmodes, int nrhs, int depth
         }
         // near field: the sources of the 3x3 neighbour leaves in tiles of 64,
         // staged in LDS, dealt round-robin to the four waves
-        int rb[9], re[9], nr = 0, total = 0;
-        for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
-            for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) {
-                const uint32_t m = morton((uint32_t)jr, (uint32_t)jz);
-                rb[nr] = sv.off[m];
-                re[nr] = sv.off[m + 1];
-                total += re[nr] - rb[nr];
-                ++nr;
-            }
+        const NearList nl(sv.off, ir, iz, nb);
+        const int total = nl.total;
         for (int tile = 0; tile < total; tile += ST) {
             __syncthreads();
             const int cnt = min(ST, total - tile);
-            for (int e = threadIdx.x; e < cnt * NMB; e += 64 * WPB) {
-                const int k = e / NMB, n = e - k * NMB;
-                int li = tile + k, rr = 0;
-                while (li >= re[rr] - rb[rr]) {
-                    li -= re[rr] - rb[rr];
-                    ++rr;
-                }
-                const int s = rb[rr] + li;
-                st_S[k * NMB + n] = Sg[(int64_t)s * Cs + n * nrhs + q];
-                if (n == 0) {
-                    st_r[k] = sv.r[s];
-                    st_z[k] = sv.z[s];
-                    st_i[k] = sinv[s];
-                }
-            }
+            stage_tile<64 * WPB, kStageLoads<NMB>>(
+                cnt, cnt * NMB, [&](int k) { return nl.source(tile + k); },
+                [&](int e) {
+                    const int k = e / NMB, n = e - k * NMB;
+                    return Sg[(int64_t)nl.source(tile + k) * Cs + n * nrhs + q];
+                },
+                sv, sinv, st_S, st_r, st_z, st_i);
             __syncthreads();
             // slot w SG + sg of every WPB SG sources (a lane past the tile's
             // end reads its group's first source and adds nothing)
@@ -1417,34 +1481,19 @@ __device__ __forceinline__ void leaf_q_body(int nmodes, int nrhs, int depth, dou
     const double inv_r = fast_rcp(r);
     Acc<NMB, 0> A;
     A.zero();
-    int rb[9], re[9], nr = 0, total = 0;
-    for (int jr = max(ir - 1, 0); jr <= min(ir + 1, nb - 1); ++jr)
-        for (int jz = max(iz - 1, 0); jz <= min(iz + 1, nb - 1); ++jz) {
-            const uint32_t m = morton((uint32_t)jr, (uint32_t)jz);
-            rb[nr] = sv.off[m];
-            re[nr] = sv.off[m + 1];
-            total += re[nr] - rb[nr];
-            ++nr;
-        }
+    const NearList nl(sv.off, ir, iz, nb);
+    const int total = nl.total;
     for (int tile = 0; tile < total; tile += ST) {
         __syncthreads();
         const int cnt = min(ST, total - tile);
-        for (int e = threadIdx.x; e < cnt * NMB * QP; e += 64 * QP) {
-            const int k = e / (NMB * QP), rem = e - k * (NMB * QP);
-            const int n = rem / QP, qq = rem - (rem / QP) * QP;
-            int li = tile + k, rr = 0;
-            while (li >= re[rr] - rb[rr]) {
-                li -= re[rr] - rb[rr];
-                ++rr;
-            }
-            const int src = rb[rr] + li;
-            st_S[e] = qq < nrhs ? Sg[(int64_t)src * Cs + n * nrhs + qq] : make_double2(0.0, 0.0);
-            if (rem == 0) {
-                st_r[k] = sv.r[src];
-                st_z[k] = sv.z[src];
-                st_i[k] = sinv[src];
-            }
-        }
+        stage_tile<64 * QP, kStageLoads<NMB>>(
+            cnt, cnt * NMB * QP, [&](int k) { return nl.source(tile + k); },
+            [&](int e) {
+                const int k = e / (NMB * QP), rem = e - k * (NMB * QP);
+                const int n = rem / QP, qq = rem - (rem / QP) * QP;
+                return qq < nrhs ? Sg[(int64_t)nl.source(tile + k) * Cs + n * nrhs + qq] : make_double2(0.0, 0.0);
+            },
+            sv, sinv, st_S, st_r, st_z, st_i);
         __syncthreads();
         for (int k0 = 0; k0 < cnt; k0 += QP) {
             // this lane's pair: its target with source k0 + q
@@ -1573,16 +1622,13 @@ __global__ __launch_bounds__(64 * PairShape<NMB>::WPB) void k_direct(int nmodes,
         for (int64_t tile = 0; tile < ns; tile += ST) {
             __syncthreads();
             const int cnt = (int)min((int64_t)ST, ns - tile);
-            for (int e = threadIdx.x; e < cnt * NMB; e += 64 * WPB) {
-                const int k = e / NMB, n = e - k * NMB;
-                const int64_t s = tile + k;
-                st_S[k * NMB + n] = Sg[s * Cs + n * nrhs + q];
-                if (n == 0) {
-                    st_r[k] = sv.r[s];
-                    st_z[k] = sv.z[s];
-                    st_i[k] = sinv[s];
-                }
-            }
+            stage_tile<64 * WPB, kStageLoads<NMB>>(
+                cnt, cnt * NMB, [&](int k) { return tile + k; },
+                [&](int e) {
+                    const int k = e / NMB, n = e - k * NMB;
+                    return Sg[(tile + k) * Cs + n * nrhs + q];
+                },
+                sv, sinv, st_S, st_r, st_z, st_i);
             __syncthreads();
             for (int k = w; k < cnt; k += WPB) {
                 const double r1 = st_r[k], x = z - st_z[k];
