@@ -161,6 +161,37 @@ def test_near_shared_rhs(nmodes, nrhs, overlap):
     plan.close()
 
 
+def _sparse_clusters(seed):
+    """Sources in a few tight clusters (two corners of the square, two
+    diagonal neighbours of a central leaf) plus a sparse scatter, field points
+    over the whole box: most leaves' 3 x 3 neighbourhoods have empty or
+    out-of-domain leaves between occupied ones."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 16                                   # a depth-4 leaf of the unit square
+    parts_r, parts_z = [], []
+    for (cr, cz, n) in [(0.2 + 0.3 * h, -0.5 + 0.3 * h, 30), (1.2 - 0.3 * h, 0.5 - 0.3 * h, 30),
+                        (0.7 - 0.5 * h, -0.5 * h, 25), (0.7 + 1.5 * h, 1.5 * h, 25)]:
+        parts_r.append(cr + 0.2 * h * rng.uniform(-1, 1, n))
+        parts_z.append(cz + 0.2 * h * rng.uniform(-1, 1, n))
+    parts_r.append(rng.uniform(0.2, 1.2, 40))
+    parts_z.append(rng.uniform(-0.5, 0.5, 40))
+    r, z = np.concatenate(parts_r), np.concatenate(parts_z)
+    rf, zf = rng.uniform(0.2, 1.2, 400), rng.uniform(-0.5, 0.5, 400)
+    return r, z, rf, zf, rng
+
+
+@gpu
+@pytest.mark.parametrize("nmodes,nrhs", [(17, 1), (12, 1), (24, 1), (9, 1), (17, 3), (24, 2), (40, 1)])
+def test_sparse_neighbour_leaves(nmodes, nrhs):
+    """Near-field source lists with empty and missing neighbour leaves between
+    occupied ones, for every source-staging depth (mode buckets 9, 12, 17,
+    24, 48) and both near-field kernels (one or several right-hand sides)."""
+    need_gpu()
+    r, z, rf, zf, rng = _sparse_clusters(1300 + nmodes + nrhs)
+    S = inputs.complex_normal(rng, (nrhs, nmodes, r.size))
+    _check(r, z, rf, zf, S, 10, 4)
+
+
 @gpu
 @pytest.mark.parametrize("nmodes", [11, 20, 40])
 def test_mode_buckets(nmodes):
